@@ -1,0 +1,448 @@
+// Batches: several FP32 fused plans (uneven shapes allowed) advanced in
+// lockstep, one fused launch per step for all of them, plus one probe and
+// one DFT launch covering every instance.  This is how the per-port runs of
+// one S-matrix (Sec. II-A: one incident and one total run per driving port)
+// and the variants of a geometry sweep share the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+
+
+namespace fdtd {
+
+// shared with plan.cpp
+void plan_bind_slice(Plan &P, char *base, size_t bytes, hipStream_t s);
+void plan_reset(Plan &P, hipStream_t s);
+void plan_finalize(Plan &P);
+DevProbes plan_dev_probes(const Plan &P);
+DevDft plan_dev_dft(const Plan &P);
+
+namespace {
+
+struct BatchError : std::runtime_error {
+    fdtd_status code;
+    BatchError(fdtd_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define BREQUIRE(cond, code, msg)                          \
+    do {                                                   \
+        if (!(cond)) throw BatchError((code), (msg));      \
+    } while (0)
+
+void hcheck(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw BatchError(FDTD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <class F>
+fdtd_status bguard(Batch *b, F &&f)
+{
+    try {
+        f();
+        if (b) b->err.clear();
+        return FDTD_OK;
+    } catch (const BatchError &e) {
+        if (b) b->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (b) b->err = "host allocation failed";
+        return FDTD_E_NOMEM;
+    } catch (const std::exception &e) {
+        if (b) b->err = e.what();
+        return FDTD_E_INVALID_ARG;
+    }
+}
+
+// Device tables of a bound batch (offsets inside its workspace):
+// [grids parity 0][grids parity 1][block_start][probes][dft]
+struct Tables {
+    size_t grids[2], starts, probes, dft, bytes;
+};
+
+Tables table_layout(int n)
+{
+    Tables t{};
+    size_t cur = 0;
+    t.grids[0] = cur; cur = al256(cur + sizeof(DevGrid<float>) * n);
+    t.grids[1] = cur; cur = al256(cur + sizeof(DevGrid<float>) * n);
+    t.starts = cur; cur = al256(cur + sizeof(int32_t) * n);
+    t.probes = cur; cur = al256(cur + sizeof(DevProbes) * n);
+    t.dft = cur; cur = al256(cur + sizeof(DevDft) * n);
+    t.bytes = cur;
+    return t;
+}
+
+void compute_blocks(Batch &B)
+{
+    B.block_start.assign(B.plans.size(), 0);
+    int32_t total = 0;
+    for (size_t q = 0; q < B.plans.size(); ++q) {
+        B.block_start[q] = total;
+        const Plan &P = *B.plans[q];
+        total += fused_tiles(P.g.nx, P.g.ny, P.g.nz, B.cfg);
+    }
+    B.total_blocks = total;
+}
+
+// Upload the instance tables for the current parity of the member plans.
+void upload_tables(Batch &B, hipStream_t s)
+{
+    const int n = (int)B.plans.size();
+    const Tables t = table_layout(n);
+    std::vector<DevGrid<float>> g0(n), g1(n);
+    std::vector<DevProbes> pr(n);
+    std::vector<DevDft> df(n);
+    for (int q = 0; q < n; ++q) {
+        Plan &P = *B.plans[q];
+        const int keep = P.parity;
+        P.parity = 0;
+        g0[q] = P.dev_grid<float>();
+        P.parity = 1;
+        g1[q] = P.dev_grid<float>();
+        P.parity = keep;
+        pr[q] = plan_dev_probes(P);
+        df[q] = plan_dev_dft(P);
+    }
+    compute_blocks(B);
+    char *base = B.base + B.r_table.off;
+    hcheck(hipMemcpyAsync(base + t.grids[0], g0.data(), sizeof(DevGrid<float>) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipMemcpyAsync(base + t.grids[1], g1.data(), sizeof(DevGrid<float>) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipMemcpyAsync(base + t.starts, B.block_start.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipMemcpyAsync(base + t.probes, pr.data(), sizeof(DevProbes) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipMemcpyAsync(base + t.dft, df.data(), sizeof(DevDft) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipStreamSynchronize(s), "table sync");
+}
+
+void batch_flush(Batch &B, hipStream_t s)
+{
+    Plan &P0 = *B.plans[0];
+    if (P0.step > P0.dft_n) {
+        const Tables t = table_layout((int)B.plans.size());
+        hcheck(launch_dft_batch(reinterpret_cast<const DevDft *>(B.base + B.r_table.off + t.dft),
+                                (int)B.plans.size(), B.max_probes, B.max_nf, P0.dft_n + 1,
+                                P0.step - P0.dft_n, s), "batch dft");
+        for (Plan *P : B.plans) P->dft_n = P0.step;
+    }
+}
+
+void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
+{
+    BREQUIRE(B.bound, FDTD_E_STATE, "batch not bound");
+    BREQUIRE(nsteps >= 0, FDTD_E_INVALID_ARG, "negative step count");
+    const int n = (int)B.plans.size();
+    const Tables t = table_layout(n);
+    char *tb = B.base + B.r_table.off;
+    const int32_t *starts = reinterpret_cast<const int32_t *>(tb + t.starts);
+    const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes);
+    Plan &P0 = *B.plans[0];
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
+        hipEvent_t e0, e1;
+        hcheck(B.timer.slot(e0, e1), "timer");
+        hcheck(launch_fused_batch(g, starts, n, B.total_blocks, B.cfg, P0.step, s, e0, e1),
+               "batch step");
+        for (Plan *P : B.plans) P->parity = 1 - P->parity;
+        const DevGrid<float> *gc = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
+        hcheck(launch_probe_batch(gc, probes, n, B.max_probes, P0.step + 1, s), "batch probe");
+        for (Plan *P : B.plans) P->step += 1;
+        if (P0.step - P0.dft_n >= P0.K) batch_flush(B, s);
+    }
+    batch_flush(B, s);
+}
+
+// ---- autotuner -------------------------------------------------------------
+// Candidates: tile rows x z-chunk (1 << 20 = a whole column per block).
+const int TUNE_ROWS[] = {1, 2, 4, 8, 16};
+const int TUNE_Z[] = {8, 16, 32, 64, 1 << 20};
+
+// Key: the shapes of the member grids, in order.
+std::string cache_key(const Batch &B)
+{
+    std::string k;
+    for (const Plan *P : B.plans) {
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "%dx%dx%d;", P->g.nx, P->g.ny, P->g.nz);
+        k += buf;
+    }
+    return k;
+}
+
+std::string device_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    return prop.gcnArchName;
+}
+
+// The cache is a JSON object written one entry per line:
+//   {
+//   "gfx950:...|400x120x80;": [4, 32, 0.0312],
+//   ...
+//   }
+// (rows, z-chunk, milliseconds per step).  Unknown lines are ignored.
+std::vector<std::pair<std::string, std::string>> cache_read(const char *path)
+{
+    std::vector<std::pair<std::string, std::string>> out;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string s(line);
+        const size_t q0 = s.find('"'), q1 = s.find("\": [");
+        const size_t b1 = s.find(']');
+        if (q0 == std::string::npos || q1 == std::string::npos || b1 == std::string::npos) continue;
+        out.emplace_back(s.substr(q0 + 1, q1 - q0 - 1), s.substr(q1 + 4, b1 - q1 - 4));
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int &rows, int &z)
+{
+    for (const auto &e : cache_read(path)) {
+        if (e.first != key) continue;
+        double ms = 0;
+        if (std::sscanf(e.second.c_str(), "%d , %d , %lf", &rows, &z, &ms) >= 2) {
+            const bool ok_rows = rows == 1 || rows == 2 || rows == 4 || rows == 8 || rows == 16;
+            return ok_rows && z >= 1;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char *path, const std::string &key, int rows, int z, double ms)
+{
+    auto entries = cache_read(path);
+    char val[128];
+    std::snprintf(val, sizeof val, "%d, %d, %.6g", rows, z, ms);
+    bool found = false;
+    for (auto &e : entries)
+        if (e.first == key) { e.second = val; found = true; }
+    if (!found) entries.emplace_back(key, val);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    for (size_t q = 0; q < entries.size(); ++q)
+        std::fprintf(f, "\"%s\": [%s]%s\n", entries[q].first.c_str(), entries[q].second.c_str(),
+                     q + 1 < entries.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+}  // namespace fdtd
+
+using namespace fdtd;
+
+extern "C" {
+
+fdtd_status fdtd_batch_create(fdtd_plan *const *plans, int32_t n, fdtd_batch **out)
+{
+    if (!plans || n < 1 || !out) return FDTD_E_INVALID_ARG;
+    *out = nullptr;
+    fdtd_batch *b = new (std::nothrow) fdtd_batch();
+    if (!b) return FDTD_E_NOMEM;
+    const fdtd_status st = bguard(b, [&]() {
+        for (int q = 0; q < n; ++q) {
+            Plan *P = plans[q];
+            BREQUIRE(P, FDTD_E_INVALID_ARG, "null plan");
+            BREQUIRE(P->g.kernel == FDTD_KERNEL_FUSED && P->g.precision == FDTD_FP32,
+                     FDTD_E_UNSUPPORTED, "batches take FP32 fused plans");
+            BREQUIRE(!P->bound && !P->in_batch, FDTD_E_STATE, "plan already bound");
+            plan_finalize(*P);
+            b->plans.push_back(P);
+            b->max_probes = std::max(b->max_probes, P->nprobe());
+            b->max_nf = std::max(b->max_nf, P->nf());
+        }
+        for (int q = 0; q < n; ++q)
+            for (int r = q + 1; r < n; ++r)
+                BREQUIRE(plans[q] != plans[r], FDTD_E_INVALID_ARG, "plan listed twice");
+        compute_blocks(*b);
+    });
+    if (st != FDTD_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_batch_workspace_size(fdtd_batch *batch, size_t *bytes)
+{
+    if (!batch || !bytes) return FDTD_E_INVALID_ARG;
+    size_t cur = 0;
+    for (Plan *P : batch->plans) cur = al256(cur + P->ws_bytes);
+    batch->r_table.off = cur;
+    batch->r_table.bytes = table_layout((int)batch->plans.size()).bytes;
+    batch->ws_bytes = cur + batch->r_table.bytes;
+    *bytes = batch->ws_bytes;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_batch_bind(fdtd_batch *batch, void *dptr, size_t bytes, void *stream)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        Batch &B = *batch;
+        size_t need = 0;
+        BREQUIRE(fdtd_batch_workspace_size(batch, &need) == FDTD_OK, FDTD_E_INVALID_ARG, "size");
+        BREQUIRE(dptr && ((uintptr_t)dptr & 255) == 0, FDTD_E_INVALID_ARG, "workspace null or misaligned");
+        BREQUIRE(bytes >= need, FDTD_E_NOMEM, "workspace smaller than fdtd_batch_workspace_size");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        B.base = static_cast<char *>(dptr);
+        size_t cur = 0;
+        for (Plan *P : B.plans) {
+            try {
+                plan_bind_slice(*P, B.base + cur, P->ws_bytes, s);
+            } catch (const std::exception &e) {
+                throw BatchError(FDTD_E_HIP, std::string("binding a member plan: ") + e.what());
+            }
+            P->in_batch = true;
+            cur = al256(cur + P->ws_bytes);
+        }
+        upload_tables(B, s);
+        B.bound = true;
+    });
+}
+
+fdtd_status fdtd_batch_reset(fdtd_batch *batch, void *stream)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        BREQUIRE(batch->bound, FDTD_E_STATE, "batch not bound");
+        for (Plan *P : batch->plans) plan_reset(*P, static_cast<hipStream_t>(stream));
+    });
+}
+
+fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() { batch_run(*batch, nsteps, static_cast<hipStream_t>(stream)); });
+}
+
+fdtd_status fdtd_batch_get_config(const fdtd_batch *batch, int32_t *rows, int32_t *zchunk)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    if (rows) *rows = batch->cfg.rows;
+    if (zchunk) *zchunk = batch->cfg.zchunk;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t rows, int32_t zchunk)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        BREQUIRE(rows == 1 || rows == 2 || rows == 4 || rows == 8 || rows == 16,
+                 FDTD_E_INVALID_ARG, "tile rows must be 1, 2, 4, 8 or 16");
+        BREQUIRE(zchunk >= 1, FDTD_E_INVALID_ARG, "z-chunk must be positive");
+        batch->cfg.rows = rows;
+        batch->cfg.zchunk = zchunk;
+        compute_blocks(*batch);
+        if (batch->bound) upload_tables(*batch, nullptr);
+    });
+}
+
+fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,
+                                void *stream, int32_t *best_index)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        Batch &B = *batch;
+        BREQUIRE(B.bound, FDTD_E_STATE, "batch not bound");
+        BREQUIRE(trial_steps >= 1, FDTD_E_INVALID_ARG, "trial_steps must be >= 1");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const std::string key = device_name() + "|" + cache_key(B);
+        int cached_rows = 0, cached_z = 0;
+        if (cache_path && cache_lookup(cache_path, key, cached_rows, cached_z)) {
+            B.cfg.rows = cached_rows;
+            B.cfg.zchunk = cached_z;
+            upload_tables(B, s);
+            if (best_index) *best_index = -1;
+            return;
+        }
+        hipEvent_t a, b;
+        hcheck(hipEventCreate(&a), "event");
+        hcheck(hipEventCreate(&b), "event");
+        const LaunchCfg keep = B.cfg;
+        const bool keep_timing = B.timer.on;
+        B.timer.on = false;
+        float best = 1e30f;
+        int best_i = -1, idx = 0;
+        LaunchCfg best_cfg = keep;
+        for (int r : TUNE_ROWS)
+            for (int z : TUNE_Z) {
+                B.cfg.rows = r;
+                B.cfg.zchunk = z;
+                upload_tables(B, s);
+                batch_run(B, 1, s);   // warm-up
+                hcheck(hipEventRecord(a, s), "event");
+                batch_run(B, trial_steps, s);
+                hcheck(hipEventRecord(b, s), "event");
+                hcheck(hipEventSynchronize(b), "event sync");
+                float ms = 0;
+                hcheck(hipEventElapsedTime(&ms, a, b), "event time");
+                if (ms < best) { best = ms; best_i = idx; best_cfg = B.cfg; }
+                ++idx;
+            }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        B.timer.on = keep_timing;
+        B.cfg = best_cfg;
+        upload_tables(B, s);
+        for (Plan *P : B.plans) plan_reset(*P, s);
+        hcheck(hipStreamSynchronize(s), "sync");
+        if (cache_path) cache_store(cache_path, key, best_cfg.rows, best_cfg.zchunk, best / trial_steps);
+        if (best_index) *best_index = best_i;
+    });
+}
+
+fdtd_status fdtd_batch_set_timing(fdtd_batch *batch, int32_t enable)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        hcheck(batch->timer.drain(), "timer drain");
+        batch->timer.reset();
+        batch->timer.on = enable != 0;
+    });
+}
+
+fdtd_status fdtd_batch_get_kernel_time(fdtd_batch *batch, double *ms, int64_t *launches)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        hcheck(batch->timer.drain(), "timer drain");
+        if (ms) *ms = batch->timer.ms;
+        if (launches) *launches = batch->timer.launches;
+    });
+}
+
+const char *fdtd_batch_last_error(const fdtd_batch *batch) { return batch ? batch->err.c_str() : ""; }
+
+void fdtd_batch_destroy(fdtd_batch *batch)
+{
+    if (!batch) return;
+    for (Plan *P : batch->plans) {
+        P->in_batch = false;
+        P->bound = false;
+    }
+    batch->timer.destroy();
+    delete batch;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+
+namespace fdtd {
+
+// Auxiliary (convolutional PML) arrays, one per (field component,
+// derivative axis) pair.
+enum PsiId {
+    PSI_HXY, PSI_HXZ, PSI_HYZ, PSI_HYX, PSI_HZX, PSI_HZY,
+    PSI_EXY, PSI_EXZ, PSI_EYZ, PSI_EYX, PSI_EZX, PSI_EZY, PSI_COUNT
+};
+
+// Per-axis profile tables, each n_axis long: E entries sit on integer
+// positions, H entries half a cell further along the axis.
+enum ProfId { PR_BE, PR_CE, PR_KE, PR_BH, PR_CH, PR_KH, PR_COUNT };
+
+// Everything a field-update kernel needs about one grid.  Plain data so it
+// can be passed by value or stored in a device table.
+//
+// Field storage: element (i, j, k), i in [-1, nx], j in [-1, ny],
+// k in [-1, nz], sits at  off + i + px*j + px*py*k  with py = ny + 2; the
+// guard layer stays zero.  Only i < nx, j < ny, k < nz is ever written: on
+// the upper faces every component is either absent or tangential-PEC zero.
+// Material ids: i + px*(j + ny*k) for the computed range.
+// Auxiliary arrays live only inside the layers:
+//   x-layers  xs + Lx*(j + ny*k)   xs = i (i < lo) or i - nx + Lx
+//   y-layers  i + px*(ys + Ly*k)
+//   z-layers  i + px*(j + ny*zs)
+template <typename T>
+struct DevGrid {
+    T *E[3], *H[3];          // fields read this step
+    T *Eo[3], *Ho[3];        // fields written this step (== E/H in place)
+    const void *ids[3];      // uint8 or uint16 per edge
+    const T *lut[3];         // per component [id][4] = Ca, Cb/d_first, Cb/d_second, 0
+    T *psi[PSI_COUNT];       // auxiliaries read this step
+    T *psi_o[PSI_COUNT];     // auxiliaries written this step (== psi in place)
+    const T *prof[3];        // per axis: PR_COUNT tables of n_axis entries
+    int64_t off;
+    int32_t nx, ny, nz, px, py;
+    int32_t id16;
+    int32_t lo[3], hi[3];    // layer cells on the low / high face of each axis
+    T ch[3];                 // dt / (mu0 d_axis)
+    // soft source on Ez
+    int32_t src_kind;
+    int32_t src_box[6];
+    double src_t0, src_w, src_fc, src_tau, src_amp, dt;
+};
+
+// Probe tables: every probe is a weighted sum of field samples.
+struct DevProbes {
+    const int64_t *toff;     // element offsets into a field array
+    const int32_t *tcomp;    // 0..5 = Ex..Hz
+    const double *tw;        // weights
+    const int32_t *range;    // per probe: V terms [r0, r1), I terms [r2, r3)
+    double *hist;            // [probe][2][K]
+    int32_t K;
+    int32_t nprobe;
+};
+
+struct LaunchCfg {
+    int32_t rows = 4;        // tile rows (y) per block of the fused kernel
+    int32_t zchunk = 32;     // planes marched per block
+};
+
+// ---------------------------------------------------------------------------
+// host-side plan
+// ---------------------------------------------------------------------------
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+// Pool of HIP event pairs that bracket field-update launches.  A pair is
+// read back only when it is about to be reused (or on drain), so timing
+// never stalls the launch queue.
+struct KernelTimer {
+    static constexpr size_t SLOTS = 512;
+    bool on = false;
+    double ms = 0;
+    int64_t launches = 0;
+    std::vector<hipEvent_t> ev;   // 2 per slot
+    std::vector<char> used;
+    size_t next = 0;
+    hipError_t slot(hipEvent_t &a, hipEvent_t &b);
+    hipError_t drain();
+    void reset();
+    void destroy();
+};
+
+struct Plan {
+    fdtd_grid g{};
+    std::vector<uint8_t> cells;
+    std::vector<fdtd_material> mats;
+    fdtd_boundary bnd{};
+    std::vector<fdtd_port> ports;
+    struct Point { int32_t comp, i, j, k; };
+    std::vector<Point> points;
+    fdtd_source src{};
+    std::vector<double> freqs;
+
+    // derived at finalize
+    bool finalized = false;
+    double dt = 0, eps0 = 0, mu0 = 0, c0 = 0;
+    int32_t px = 0, py = 0, pz = 0;
+    size_t field_elems = 0, id_elems = 0;
+    int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    int32_t id16 = 0;
+    std::vector<uint16_t> ids[3];
+    std::vector<double> lut[3];          // [id][4]
+    std::vector<double> prof[3];         // [PR_COUNT][n_axis]
+    size_t psi_elems[PSI_COUNT] = {};
+    std::vector<int64_t> toff;
+    std::vector<int32_t> tcomp;
+    std::vector<double> tw;
+    std::vector<int32_t> prange;
+    int32_t K = 512;                     // probe history ring length
+    int32_t nbuf = 1;                    // field buffers (2 for ping-pong)
+    size_t elt = 4;                      // bytes per field value
+
+    // workspace layout (offsets relative to the bound pointer)
+    Region r_ids[3], r_lut[3], r_prof[3], r_toff, r_tcomp, r_tw, r_range, r_freq;
+    Region r_E[2][3], r_H[2][3], r_psi[2][PSI_COUNT], r_hist, r_acc;
+    Region r_static, r_mut;
+    size_t ws_bytes = 0;
+
+    // bound state
+    char *base = nullptr;
+    bool bound = false;
+    bool in_batch = false;
+    int64_t step = 0;                    // completed steps
+    int64_t dft_n = 0;                   // last sample folded into the DFT
+    int32_t parity = 0;                  // which field buffer holds the current level
+    LaunchCfg cfg;
+
+    KernelTimer timer;
+
+    std::string err;
+
+    int nprobe() const { return (int)(ports.size() + points.size()); }
+    int nf() const { return (int)freqs.size(); }
+    template <typename T> DevGrid<T> dev_grid() const;
+};
+
+struct Batch {
+    std::vector<Plan *> plans;
+    LaunchCfg cfg;
+    Region r_table;
+    size_t ws_bytes = 0;
+    char *base = nullptr;
+    bool bound = false;
+    std::vector<int32_t> block_start;   // per plan: first block of its tiles
+    int32_t total_blocks = 0;
+    int32_t max_probes = 0;
+    int32_t max_nf = 0;
+    KernelTimer timer;
+    std::string err;
+};
+
+// DFT accumulation for one grid's probes.
+struct DevDft {
+    const double *hist;      // [probe][2][K]
+    double *acc;             // [probe][2][nf][2]
+    const double *freqs;
+    int32_t nf, nprobe, K;
+    double dt;
+};
+
+// kernel launchers (kernels.hip / fused.hip)
+template <typename T>
+hipError_t launch_plain_step(const DevGrid<T> &d, int64_t level, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_probe(const DevGrid<T> &d, const DevProbes &p, int64_t sample, hipStream_t s);
+hipError_t launch_dft(const DevDft &d, int64_t n_first, int64_t count, hipStream_t s);
+hipError_t launch_fused_step(const DevGrid<float> &d, const LaunchCfg &cfg, int64_t level,
+                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fused_batch(const DevGrid<float> *grids_dev, const int32_t *block_start_dev,
+                              int32_t ninst, int32_t total_blocks, const LaunchCfg &cfg,
+                              int64_t level, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
+                              int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
+hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,
+                            int32_t max_nf, int64_t n_first, int64_t count, hipStream_t s);
+int32_t fused_tiles(int32_t nx, int32_t ny, int32_t nz, const LaunchCfg &cfg);
+
+}  // namespace fdtd
+
+// The opaque handles of the C interface are the host-side objects.
+struct fdtd_plan : fdtd::Plan {};
+struct fdtd_batch : fdtd::Batch {};

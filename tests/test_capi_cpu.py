@@ -1,0 +1,181 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function
+include/fdtd.h declares, validates its arguments, and its host FP64
+arithmetic (time step, post-processing) agrees with the oracle's."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import post
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fd():
+    from paper_2208_04371_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2208_04371_amd as fd
+    fd.lib()
+    return fd
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(fdtd_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol(fd):
+    names = _declared()
+    assert len(names) >= 39
+    L = C.CDLL(fd._capi.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert names <= set(fd._capi.SIGNATURES), names - set(fd._capi.SIGNATURES)
+
+
+def test_status_strings(fd):
+    L = fd.lib()
+    assert L.fdtd_status_string(0) == b"ok"
+    assert L.fdtd_status_string(-6) == b"diverged"
+
+
+def test_create_rejects_bad_grids(fd):
+    with pytest.raises(fd.FdtdError) as e:
+        fd._plan_create = None
+        from paper_2208_04371_amd import fdtd_plan_create
+        fdtd_plan_create(0, 10, 10, 1, 1, 1, 0.9)
+    assert e.value.code == -1
+    from paper_2208_04371_amd import fdtd_plan_create
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_create(10, 10, 10, 1, 1, 1, 0.9, precision=fd.FP64, kernel=fd.KERNEL_FUSED)
+    assert e.value.code == -3
+    with pytest.raises(fd.FdtdError):
+        fdtd_plan_create(10, 10, 10, -1, 1, 1, 0.9)
+
+
+def test_call_order_and_argument_errors(fd):
+    from paper_2208_04371_amd import (describe, fdtd_plan_add_port, fdtd_plan_create,
+                                      fdtd_plan_destroy, fdtd_plan_workspace_size, fdtd_run,
+                                      fdtd_plan_set_materials)
+    p = W.small_microstrip()
+    h = describe(p)
+    # run before bind
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_run(h, 10, stream=0)
+    assert e.value.code == -2
+    # port whose current loop would leave the grid
+    h2 = fdtd_plan_create(20, 20, 20, 1, 1, 1, 0.9, units=fd.NORMALIZED)
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_add_port(h2, 5, 1, 0, 4, 2, 4)
+    assert e.value.code == -1
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_add_port(h2, 5, 2, 3, 6, 2, 4)
+    assert e.value.code == -1
+    # material id out of range
+    cells = np.full((20, 20, 20), 3, np.uint8)
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_set_materials(h2, cells, [W.Material(1.0)])
+    assert e.value.code == -1
+    # workspace query before materials
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_workspace_size(h2)
+    assert e.value.code == -2
+    assert fdtd_plan_workspace_size(h) > 0
+    # describe refuses magnetic walls, which only the oracle models
+    with pytest.raises(fd.FdtdError):
+        describe(W.parallel_plate())
+    fdtd_plan_destroy(h)
+    fdtd_plan_destroy(h2)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.pec_cavity(),
+    lambda: W.single_microstrip(),
+    lambda: W.large_line(),
+    lambda: W.small_microstrip(),
+])
+def test_time_step_agrees_with_oracle(fd, make):
+    from paper_2208_04371_amd import describe, fdtd_plan_destroy, fdtd_plan_get_dt, \
+        fdtd_plan_workspace_size
+    p = make()
+    h = describe(p)
+    fdtd_plan_workspace_size(h)
+    dt = fdtd_plan_get_dt(h)
+    fdtd_plan_destroy(h)
+    o = oracle.Oracle(W.Problem(name="t", nx=2, ny=2, nz=2, dx=p.dx, dy=p.dy, dz=p.dz,
+                                courant=p.courant, normalized=p.normalized,
+                                materials=[W.Material()], cells=np.zeros((2, 2, 2), np.uint8),
+                                faces=(0,) * 6))
+    assert dt == pytest.approx(o.dt, rel=1e-15)
+
+
+def test_workspace_grows_with_ping_pong(fd):
+    from paper_2208_04371_amd import describe, fdtd_plan_destroy, fdtd_plan_workspace_size
+    p = W.small_microstrip()
+    hf = describe(p, fused=True)
+    hp = describe(p, fused=False)
+    sf, sp = fdtd_plan_workspace_size(hf), fdtd_plan_workspace_size(hp)
+    assert sf > 1.8 * sp
+    fdtd_plan_destroy(hf)
+    fdtd_plan_destroy(hp)
+
+
+def _random_protocol(rng, n, nf):
+    c = lambda *s: rng.normal(size=s) + 1j * rng.normal(size=s)
+    Vinc = c(n, nf)
+    Iinc = Vinc / (rng.uniform(10, 90, (n, nf)) + 1j * rng.uniform(-10, 10, (n, nf)))
+    Vtot = c(n, n, nf) * 0.4
+    for j in range(n):
+        Vtot[j, j] = Vinc[j] * (1 + 0.3 * c(nf))
+    return Vinc, Iinc, Vtot
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_sparams_matches_oracle_post(fd, n):
+    rng = np.random.default_rng(40 + n)
+    nf = 9
+    f = np.linspace(1e12, 9e12, nf)
+    Vinc, Iinc, Vtot = _random_protocol(rng, n, nf)
+    got = fd.fdtd_sparams(f, Vinc, Iinc, Vtot)
+    ref = post.sparams(f, Vinc, Iinc, Vtot)
+    for key in ("S_star", "S", "Zr"):
+        assert np.max(np.abs(got[key] - ref[key])) < 1e-12 * max(1, np.max(np.abs(ref[key])))
+    if n == 2:
+        assert np.max(np.abs(got["Z0"] - ref["Z0"])) < 1e-10 * np.max(np.abs(ref["Z0"]))
+    # phase delays agree where the unwrapped phase is smooth enough to define them
+    assert np.allclose(got["tau"], ref["tau"], rtol=1e-9, atol=1e-25)
+
+
+def test_sparams_uniform_line_closed_form(fd):
+    """Library post-processing of a reflectionless 25 ohm line matches eq. 7
+    (typo fixed) after renormalization to 50 ohm, and Z0 = 25 ohm."""
+    f = np.linspace(1e9, 60e9, 40)
+    tau = 30e-12
+    k = np.exp(-2j * np.pi * f * tau)
+    Vinc = np.stack([np.ones_like(k), np.ones_like(k)])
+    Iinc = Vinc / 25.0
+    Vtot = np.stack([np.stack([Vinc[0], k]), np.stack([k, Vinc[1]])])
+    r = fd.fdtd_sparams(f, Vinc, Iinc, Vtot)
+    s11, s21 = post.lossless_line_s(-1.0 / 3.0, k)
+    assert np.max(np.abs(r["S"][:, 0, 0] - s11)) < 1e-13
+    assert np.max(np.abs(r["S"][:, 1, 0] - s21)) < 1e-13
+    assert np.max(np.abs(r["Z0"] - 25.0)) < 1e-10
+    assert np.max(np.abs(r["tau"][:, 1, 0] / tau - 1)) < 1e-12
+
+
+def test_sparams_rejects_bad_input(fd):
+    with pytest.raises(fd.FdtdError) as e:
+        fd.fdtd_sparams(np.zeros(0), np.zeros((1, 0)), np.zeros((1, 0)), np.zeros((1, 1, 0)))
+    assert e.value.code == -1

@@ -1,0 +1,255 @@
+"""GPU path vs the FP64 CPU oracle, element by element, through the C ABI.
+
+Tolerances: plain FP64 kernels agree with the oracle to 1e-10 relative
+(rounding order only); FP32 fields to a relative L2 of 1e-4, S-parameters to
+|dS| <= 1e-3 and Z0 to 0.5 %.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import post
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_04371_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2208_04371_amd as fd
+    return fd
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _fields(x):
+    return [x.field(c) for c in range(6)]
+
+
+def _field_errors(got, ref, norm="max"):
+    """Per-component error relative to the scale of its group (E or H):
+    max-norm (norm="max") or L2 over the group (norm="l2")."""
+    errs = []
+    for grp in ((0, 1, 2), (3, 4, 5)):
+        if norm == "max":
+            scale = max(np.max(np.abs(ref[c])) for c in grp)
+            errs += [float(np.max(np.abs(got[c] - ref[c])) / scale) for c in grp]
+        else:
+            scale = math.sqrt(sum(np.sum(ref[c] ** 2) for c in grp))
+            errs += [float(np.linalg.norm(got[c] - ref[c]) / scale) for c in grp]
+    return errs
+
+
+def _check_fields(sim, o, tol, norm="max"):
+    errs = _field_errors(_fields(sim), _fields(o), norm)
+    _say(f"  field errors ({norm}): " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) < tol, f"field error {max(errs):.3e} >= {tol}"
+
+
+# ---------------------------------------------------------------------------
+# plain FP64
+# ---------------------------------------------------------------------------
+
+def test_cavity_fp64_plain_matches_oracle(fd):
+    p = W.pec_cavity()
+    _say(f"cavity fp64 plain {p.nx}^3 x {p.nsteps}")
+    sim = fd.Simulation(p, fused=False)
+    sim.run()
+    o = oracle.Oracle(p).run(p.nsteps)
+    _check_fields(sim, o, 1e-10)
+    Vg, _ = sim.spectra()
+    Vo, _ = o.spectra()
+    assert _rel(Vg, Vo) < 1e-10
+
+
+def test_small_microstrip_fp64_plain_matches_oracle(fd):
+    p = W.small_microstrip(nsteps=500, fp32=False)
+    _say("small microstrip fp64 plain")
+    sim = fd.Simulation(p, fused=False)
+    sim.run()
+    o = oracle.Oracle(p).run(p.nsteps)
+    _check_fields(sim, o, 1e-10)
+    Vg, Ig = sim.spectra()
+    Vo, Io = o.spectra()
+    assert _rel(Vg, Vo) < 1e-10
+    assert _rel(Ig, Io) < 1e-10
+
+
+def test_layered_lossy_fp64_plain_matches_oracle(fd):
+    p = W.small_microstrip(nsteps=400, fp32=False, seed=9, sigma_strip=5.8e7)
+    _say("layered lossy microstrip fp64 plain")
+    sim = fd.Simulation(p, fused=False)
+    sim.run()
+    o = oracle.Oracle(p).run(p.nsteps)
+    _check_fields(sim, o, 1e-10)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_eigenmode_on_gpu(fd, fused):
+    """The TM_210 standing mode of the PEC cube evolves as cos(w n dt) with
+    the Yee dispersion relation, on the GPU too."""
+    N, m, n = 32, 2, 1
+    p = W.pec_cavity(n=N, source=False, fp32=fused)
+    sim = fd.Simulation(p, fused=fused)
+    dt = sim.dt
+    a, b = m * math.pi / N, n * math.pi / N
+    w = 2 * math.asin(dt * math.sqrt(math.sin(a / 2) ** 2 + math.sin(b / 2) ** 2)) / dt
+    kk, jj, ii = np.meshgrid(np.arange(N + 1), np.arange(N + 1), np.arange(N + 1), indexing="ij")
+    Ez = np.sin(a * ii) * np.sin(b * jj)
+    Ez[N] = 0
+    Hx = 0.5 * dt * np.sin(a * ii) * 2 * np.cos(b * (jj + 0.5)) * math.sin(b / 2)
+    Hy = -0.5 * dt * np.sin(b * jj) * 2 * np.cos(a * (ii + 0.5)) * math.sin(a / 2)
+    Hx[:, N, :] = 0; Hx[N] = 0
+    Hy[:, :, N] = 0; Hy[N] = 0
+    sim.set_field(W.EZ, Ez)
+    sim.set_field(W.HX, Hx)
+    sim.set_field(W.HY, Hy)
+    steps = 1000
+    sim.run(steps)
+    err = _rel(sim.field(W.EZ), math.cos(w * steps * dt) * Ez)
+    assert np.isfinite(err)
+    _say(f"eigenmode fused={fused} err {err:.2e}")
+    assert err < (1e-4 if fused else 1e-11)
+
+
+# ---------------------------------------------------------------------------
+# FP32 plain and fused
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def small_ref():
+    p = W.small_microstrip(nsteps=800)
+    o = oracle.Oracle(p).run(p.nsteps)
+    return p, o
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_small_microstrip_fp32_matches_oracle(fd, small_ref, fused):
+    p, o = small_ref
+    _say(f"small microstrip fp32 fused={fused}")
+    sim = fd.Simulation(p, fused=fused)
+    sim.run()
+    _check_fields(sim, o, 1e-4, norm="l2")
+    Vg, Ig = sim.spectra()
+    Vo, Io = o.spectra()
+    assert _rel(Vg, Vo) < 1e-4
+    assert _rel(Ig, Io) < 1e-4
+    rg = fd.fdtd_sparams(p.freqs, *post.single_excitation_protocol(Vg, Ig))
+    ro = post.sparams(p.freqs, *post.single_excitation_protocol(Vo, Io))
+    assert np.max(np.abs(rg["S_star"] - ro["S_star"])) < 1e-3
+    assert np.max(np.abs(rg["S"] - ro["S"])) < 1e-3
+    assert np.max(np.abs(rg["Z0"] / ro["Z0"] - 1)) < 5e-3
+
+
+@pytest.mark.parametrize("rows,zchunk", [(1, 1000), (2, 5), (4, 32), (8, 7), (16, 3)])
+def test_fused_launch_shapes_agree(fd, rows, zchunk):
+    """Every tile height and z-chunk (ragged tails in x, y and z) gives the
+    same fields as the reference launch shape."""
+    p = W.small_microstrip(nsteps=150, seed=4)
+    ref = fd.Simulation(p, fused=True, config=(4, 32)).run()
+    sim = fd.Simulation(p, fused=True, config=(rows, zchunk)).run()
+    errs = _field_errors(_fields(sim), _fields(ref))
+    assert max(errs) < 1e-6, errs
+
+
+def test_fused_equals_plain_fp32(fd):
+    p = W.small_microstrip(nsteps=300, seed=2, sigma_strip=5.8e7)
+    a = fd.Simulation(p, fused=True).run()
+    b = fd.Simulation(p, fused=False).run()
+    errs = _field_errors(_fields(a), _fields(b))
+    assert max(errs) < 1e-5, errs
+
+
+def test_fused_deterministic(fd):
+    p = W.small_microstrip(nsteps=200)
+    a = fd.Simulation(p, fused=True).run()
+    b = fd.Simulation(p, fused=True).run()
+    Va, Ia = a.spectra()
+    Vb, Ib = b.spectra()
+    assert np.array_equal(Va, Vb) and np.array_equal(Ia, Ib)
+    for comp in range(6):
+        assert np.array_equal(a.field(comp), b.field(comp)), comp
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_checkpoint_resume_bitwise(fd, fused):
+    p = W.small_microstrip(nsteps=300)
+    a = fd.Simulation(p, fused=fused).run(300)
+    b = fd.Simulation(p, fused=fused).run(137)
+    ck = b.checkpoint()
+    b.run(163)
+    c = fd.Simulation(p, fused=fused)
+    c.restore(ck)
+    c.run(163)
+    Va, Ia = a.spectra()
+    for x in (b, c):
+        Vx, Ix = x.spectra()
+        assert np.array_equal(Va, Vx) and np.array_equal(Ia, Ix)
+        for comp in range(6):
+            assert np.array_equal(a.field(comp), x.field(comp)), comp
+
+
+def test_resumed_runs_equal_one_run(fd):
+    p = W.small_microstrip(nsteps=1200)
+    a = fd.Simulation(p, fused=True).run(1200)
+    b = fd.Simulation(p, fused=True)
+    for n in (1, 511, 512, 176):
+        b.run(n)
+    assert b.step == 1200
+    Va, Ia = a.spectra()
+    Vb, Ib = b.spectra()
+    assert np.array_equal(Va, Vb) and np.array_equal(Ia, Ib)
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+def test_batch_equals_single_runs(fd):
+    probs = [W.small_microstrip(nsteps=200, ny=36 + 4 * q, seed=q) for q in range(4)]
+    probs.append(W.pec_cavity(n=20, nsteps=200, fp32=True))
+    _say("batch of 5 uneven instances")
+    bs = fd.BatchSimulation(probs)
+    bs.run(200)
+    for q, p in enumerate(probs):
+        s = fd.Simulation(p, fused=True, config=bs.get_config()).run(200)
+        Vb, Ib = bs.spectra(q)
+        Vs, Is = s.spectra()
+        assert np.array_equal(Vb, Vs) and np.array_equal(Ib, Is), f"instance {q} spectra"
+        assert np.array_equal(bs.field(q, W.EZ), s.field(W.EZ)), f"instance {q} Ez"
+
+
+# ---------------------------------------------------------------------------
+# the 400x120x80 microstrip at full size, in the benchmark's launch shape
+# ---------------------------------------------------------------------------
+
+def test_full_size_microstrip_window(fd):
+    """The full 400x120x80 grid for a 300-step window of the resolved
+    (THz) reading: every field against the oracle."""
+    p = W.single_microstrip(twin=True, nsteps=300)
+    _say("full-size microstrip window, 300 steps")
+    sim = fd.Simulation(p, fused=True).run()
+    o = oracle.Oracle(p).run(p.nsteps)
+    _check_fields(sim, o, 1e-4, norm="l2")
+    Vg, Ig = sim.spectra()
+    Vo, Io = o.spectra()
+    assert _rel(Vg, Vo) < 1e-4 and _rel(Ig, Io) < 1e-4
