@@ -245,8 +245,8 @@ fdtd_status fdtd_batch_reset(fdtd_batch *batch, void *stream);
 /* Advance every member plan by nsteps steps in lockstep.  Asynchronous. */
 fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 
-/* Choose the tile height (1, 2, 4, 8, 16 rows) and z-chunk (8, 16, 32, 64
- * planes or whole columns) of the batched kernel by timing each candidate
+/* Choose the tile height (2, 4, 8, 16 rows) and z-chunk (4, 8, 16, 32, 64
+ * planes) of the batched kernel by timing each candidate
  * for `trial_steps` steps; the member states are reset afterwards.
  * cache_path (may be NULL) names a JSON file keyed by GPU architecture and
  * member grid shapes: a hit applies the stored choice without timing
@@ -255,7 +255,9 @@ fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,
                                 void *stream, int32_t *best_index);
 
-/* Current launch configuration: tile rows per block and z-chunk length. */
+/* Launch configuration of the fused kernel: tile rows per block (2, 4, 8 or
+ * 16; a block is 64 x rows threads) and the number of z planes one block
+ * marches through (1..64).  set returns INVALID_ARG for other values. */
 fdtd_status fdtd_batch_get_config(const fdtd_batch *batch, int32_t *tile_rows,
                                   int32_t *zchunk);
 fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t tile_rows, int32_t zchunk);

@@ -167,3 +167,19 @@ def single_excitation_protocol(V: np.ndarray, I: np.ndarray):
     Iinc = np.stack([I[0], I[0]])
     Vtot = np.stack([np.stack([V[0], V[1]]), np.stack([V[1], V[0]])])
     return Vinc, Iinc, Vtot
+
+
+def protocol_from_runs(spectra):
+    """Spectra of the four runs of the per-port protocol (Sec. II-A) in the
+    arrangement ``sparams`` takes.  ``spectra`` maps "inc1", "inc2", "tot1",
+    "tot2" to (V[probe, f], I[probe, f]) with probe 0 = port 1, 1 = port 2.
+    Vinc[j], Iinc[j]: port j in the run driving port j on its uniform line;
+    Vtot[j, i]: port i in the full-circuit run driven at port j."""
+    V1, I1 = spectra["inc1"]
+    V2, I2 = spectra["inc2"]
+    T1, _ = spectra["tot1"]
+    T2, _ = spectra["tot2"]
+    Vinc = np.stack([V1[0], V2[1]])
+    Iinc = np.stack([I1[0], I2[1]])
+    Vtot = np.stack([np.stack([T1[0], T1[1]]), np.stack([T2[0], T2[1]])])
+    return Vinc, Iinc, Vtot

@@ -206,6 +206,19 @@ def fdtd_sparams(freqs, Vinc, Iinc, Vtot, z_ref=50.0):
     return {"S_star": c(Ss), "S": c(S), "Zr": c(Zr), "Z0": c(Z0) if n == 2 else None, "tau": tau}
 
 
+def protocol_from_runs(spectra):
+    """Arrange the spectra of the four runs of a 2-port's protocol ("inc1",
+    "inc2": port j driven on its uniform line; "tot1", "tot2": the full
+    circuit driven at port j; each (V[probe, f], I[probe, f]), probe 0 =
+    port 1) into the Vinc, Iinc, Vtot arrays fdtd_sparams takes."""
+    V1, I1 = spectra["inc1"]
+    V2, I2 = spectra["inc2"]
+    T1 = spectra["tot1"][0]
+    T2 = spectra["tot2"][0]
+    return (np.stack([V1[0], V2[1]]), np.stack([I1[0], I2[1]]),
+            np.stack([np.stack([T1[0], T1[1]]), np.stack([T2[0], T2[1]])]))
+
+
 # ---------------------------------------------------------------------------
 # helpers that describe a workloads.Problem through the calls above
 # ---------------------------------------------------------------------------

@@ -125,15 +125,17 @@ void upload_tables(Batch &B, hipStream_t s)
     hcheck(hipStreamSynchronize(s), "table sync");
 }
 
+// Fold the pending history samples of every member into its DFTs (all
+// members step, sample and fold in lockstep).
 void batch_flush(Batch &B, hipStream_t s)
 {
     Plan &P0 = *B.plans[0];
-    if (P0.step > P0.dft_n) {
+    if (P0.sampled > P0.dft_n) {
         const Tables t = table_layout((int)B.plans.size());
         hcheck(launch_dft_batch(reinterpret_cast<const DevDft *>(B.base + B.r_table.off + t.dft),
                                 (int)B.plans.size(), B.max_probes, B.max_nf, P0.dft_n + 1,
-                                P0.step - P0.dft_n, s), "batch dft");
-        for (Plan *P : B.plans) P->dft_n = P0.step;
+                                P0.sampled - P0.dft_n, s), "batch dft");
+        for (Plan *P : B.plans) P->dft_n = P0.sampled;
     }
 }
 
@@ -147,25 +149,35 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
     const int32_t *starts = reinterpret_cast<const int32_t *>(tb + t.starts);
     const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes);
     Plan &P0 = *B.plans[0];
+    const bool sample = B.max_probes > 0;
     for (int64_t q = 0; q < nsteps; ++q) {
         const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
         hipEvent_t e0, e1;
         hcheck(B.timer.slot(e0, e1), "timer");
-        hcheck(launch_fused_batch(g, starts, n, B.total_blocks, B.cfg, P0.step, s, e0, e1),
+        // one launch: every instance's step, plus sampling of its input level
+        hcheck(launch_fused(g, starts, n, B.total_blocks, B.cfg, P0.step, probes, B.max_probes,
+                            sample, s, e0, e1),
                "batch step");
-        for (Plan *P : B.plans) P->parity = 1 - P->parity;
+        const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
+        for (Plan *P : B.plans) {
+            P->parity = 1 - P->parity;
+            P->step += 1;
+            P->sampled = sampled;
+        }
+        if (P0.sampled - P0.dft_n >= P0.K - 1) batch_flush(B, s);
+    }
+    if (sample && P0.sampled < P0.step) {
         const DevGrid<float> *gc = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
-        hcheck(launch_probe_batch(gc, probes, n, B.max_probes, P0.step + 1, s), "batch probe");
-        for (Plan *P : B.plans) P->step += 1;
-        if (P0.step - P0.dft_n >= P0.K) batch_flush(B, s);
+        hcheck(launch_probe_batch(gc, probes, n, B.max_probes, P0.step, s), "batch probe");
+        for (Plan *P : B.plans) P->sampled = P0.step;
     }
     batch_flush(B, s);
 }
 
 // ---- autotuner -------------------------------------------------------------
 // Candidates: tile rows x z-chunk (1 << 20 = a whole column per block).
-const int TUNE_ROWS[] = {1, 2, 4, 8, 16};
-const int TUNE_Z[] = {8, 16, 32, 64, 1 << 20};
+const int TUNE_ROWS[] = {2, 4, 8, 16};
+const int TUNE_Z[] = {4, 8, 16, 32, 64};
 
 // Key: the shapes of the member grids, in order.
 std::string cache_key(const Batch &B)
@@ -217,8 +229,8 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &z)
         if (e.first != key) continue;
         double ms = 0;
         if (std::sscanf(e.second.c_str(), "%d , %d , %lf", &rows, &z, &ms) >= 2) {
-            const bool ok_rows = rows == 1 || rows == 2 || rows == 4 || rows == 8 || rows == 16;
-            return ok_rows && z >= 1;
+            const bool ok_rows = rows == 2 || rows == 4 || rows == 8 || rows == 16;
+            return ok_rows && z >= 1 && z <= 64;
         }
     }
     return false;
@@ -348,9 +360,9 @@ fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t rows, int32_t zchun
 {
     if (!batch) return FDTD_E_INVALID_ARG;
     return bguard(batch, [&]() {
-        BREQUIRE(rows == 1 || rows == 2 || rows == 4 || rows == 8 || rows == 16,
-                 FDTD_E_INVALID_ARG, "tile rows must be 1, 2, 4, 8 or 16");
-        BREQUIRE(zchunk >= 1, FDTD_E_INVALID_ARG, "z-chunk must be positive");
+        BREQUIRE(rows == 2 || rows == 4 || rows == 8 || rows == 16,
+                 FDTD_E_INVALID_ARG, "tile rows must be 2, 4, 8 or 16");
+        BREQUIRE(zchunk >= 1 && zchunk <= 64, FDTD_E_INVALID_ARG, "z-chunk must be in [1, 64]");
         batch->cfg.rows = rows;
         batch->cfg.zchunk = zchunk;
         compute_blocks(*batch);

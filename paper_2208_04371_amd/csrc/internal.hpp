@@ -47,6 +47,7 @@ struct DevGrid {
     int64_t off;
     int32_t nx, ny, nz, px, py;
     int32_t id16;
+    int32_t nlut;            // entries per LUT
     int32_t lo[3], hi[3];    // layer cells on the low / high face of each axis
     T ch[3];                 // dt / (mu0 d_axis)
     // soft source on Ez
@@ -128,6 +129,7 @@ struct Plan {
     // workspace layout (offsets relative to the bound pointer)
     Region r_ids[3], r_lut[3], r_prof[3], r_toff, r_tcomp, r_tw, r_range, r_freq;
     Region r_E[2][3], r_H[2][3], r_psi[2][PSI_COUNT], r_hist, r_acc;
+    Region r_grid;                       // fused plans: DevGrid<float> per parity + block start
     Region r_static, r_mut;
     size_t ws_bytes = 0;
 
@@ -137,6 +139,7 @@ struct Plan {
     bool in_batch = false;
     int64_t step = 0;                    // completed steps
     int64_t dft_n = 0;                   // last sample folded into the DFT
+    int64_t sampled = 0;                 // last sample written to the history ring
     int32_t parity = 0;                  // which field buffer holds the current level
     LaunchCfg cfg;
 
@@ -180,11 +183,13 @@ hipError_t launch_plain_step(const DevGrid<T> &d, int64_t level, hipStream_t s,
 template <typename T>
 hipError_t launch_probe(const DevGrid<T> &d, const DevProbes &p, int64_t sample, hipStream_t s);
 hipError_t launch_dft(const DevDft &d, int64_t n_first, int64_t count, hipStream_t s);
-hipError_t launch_fused_step(const DevGrid<float> &d, const LaunchCfg &cfg, int64_t level,
-                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused_batch(const DevGrid<float> *grids_dev, const int32_t *block_start_dev,
-                              int32_t ninst, int32_t total_blocks, const LaunchCfg &cfg,
-                              int64_t level, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// One fused step of ninst grids (device table grids_dev, first tile of each
+// in block_start_dev, ntiles tiles in all).  With sample_input the launch
+// also samples every probe of the input level `level` (if level >= 1).
+hipError_t launch_fused(const DevGrid<float> *grids_dev, const int32_t *block_start_dev,
+                        int32_t ninst, int32_t ntiles, const LaunchCfg &cfg, int64_t level,
+                        const DevProbes *probes_dev, int32_t max_probes, bool sample_input,
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
                               int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
 hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
+#include "probe.hpp"
 
 namespace fdtd {
 
@@ -154,44 +155,6 @@ __global__ void __launch_bounds__(BX *BY) k_e_plain(DevGrid<T> d, int64_t level)
 }
 
 constexpr int PROBE_THREADS = 256;
-
-// Weighted sum of field samples in FP64, fixed summation order: thread t
-// adds terms t, t+256, ... in turn, then a fixed pairwise tree.
-template <typename T>
-__device__ double probe_sum(const DevGrid<T> &d, const DevProbes &p, int r0, int r1,
-                            double *red)
-{
-    const int t = threadIdx.x;
-    double acc = 0.0;
-    for (int q = r0 + t; q < r1; q += PROBE_THREADS) {
-        const int comp = p.tcomp[q];
-        const T *F = comp < 3 ? d.E[comp] : d.H[comp - 3];   // the current level
-        acc += (double)F[p.toff[q]] * p.tw[q];
-    }
-    red[t] = acc;
-    __syncthreads();
-    for (int w = PROBE_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    const double v = red[0];
-    __syncthreads();
-    return v;
-}
-
-template <typename T>
-__device__ void probe_one(const DevGrid<T> &d, const DevProbes &p, int probe, int64_t sample,
-                          double *red)
-{
-    const int *r = p.range + 4 * probe;
-    const double v = probe_sum(d, p, r[0], r[1], red);
-    const double cur = probe_sum(d, p, r[2], r[3], red);
-    if (threadIdx.x == 0) {
-        const int64_t slot = (sample - 1) % p.K;
-        p.hist[((int64_t)probe * 2 + 0) * p.K + slot] = v;
-        p.hist[((int64_t)probe * 2 + 1) * p.K + slot] = cur;
-    }
-}
 
 template <typename T>
 __global__ void __launch_bounds__(PROBE_THREADS) k_probe(DevGrid<T> d, DevProbes p, int64_t sample)

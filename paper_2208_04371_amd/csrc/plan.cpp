@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <stdexcept>
 #include <utility>
@@ -55,6 +56,10 @@ static fdtd_status guarded(Plan *p, F &&f)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Layout of a fused plan's launch table (region r_grid).
+static constexpr size_t GRID_START_OFF = 2 * sizeof(DevGrid<float>);
+static constexpr size_t GRID_PROBES_OFF = (GRID_START_OFF + 4 + 63) & ~size_t(63);
+
 // ---------------------------------------------------------------------------
 // finalize: everything derived from the description
 // ---------------------------------------------------------------------------
@@ -77,44 +82,69 @@ static void build_coefficients(Plan &P)
         table.push_back(key);
         return id;
     };
-    auto mat = [&](int i, int j, int k) -> const fdtd_material & {
-        return P.mats[P.cells[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)]];
+    auto cell = [&](int i, int j, int k) -> uint32_t {
+        return P.cells[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
     };
+    // coefficient id of an edge from the ids of its four cells (memoized:
+    // neighbouring edges almost always share their materials)
+    std::unordered_map<uint32_t, int> memo;
+    auto coef_id = [&](uint32_t key, const uint32_t m4[4]) {
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        bool pec = false;
+        double se = 0, ss = 0;
+        for (int q = 0; q < 4; ++q) {
+            const fdtd_material &m = P.mats[m4[q]];
+            pec = pec || m.is_pec;
+            se += m.eps_r;
+            ss += m.sigma;
+        }
+        double ca = 0, cb = 0;
+        if (!pec) {
+            const double eps = P.eps0 * (se / 4.0);
+            const double sig = ss / 4.0;
+            const double half_loss = sig * P.dt / (2.0 * eps);
+            ca = (1.0 - half_loss) / (1.0 + half_loss);
+            cb = (P.dt / eps) / (1.0 + half_loss);
+        }
+        const int id = lookup(ca, cb);
+        memo.emplace(key, id);
+        return id;
+    };
+    const int pec_id = lookup(0.0, 0.0);
     for (int comp = 0; comp < 3; ++comp) {
         P.ids[comp].assign(P.id_elems, 0);
+        // the two axes across the edge
+        const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
         for (int k = 0; k < nz; ++k)
-            for (int j = 0; j < ny; ++j)
+            for (int j = 0; j < ny; ++j) {
+                uint32_t last_key = 0xffffffffu;
+                int last_id = 0;
                 for (int i = 0; i < nx; ++i) {
                     const int pos[3] = {i, j, k};
-                    bool pec = false;
-                    // the two axes across the edge
-                    const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
-                    if (pos[a1] == 0 || pos[a2] == 0) pec = true;
-                    double se = 0, ss = 0;
-                    if (!pec) {
-                        for (int d2 = -1; d2 <= 0 && !pec; ++d2)
-                            for (int d1 = -1; d1 <= 0 && !pec; ++d1) {
+                    int id;
+                    if (pos[a1] == 0 || pos[a2] == 0) {
+                        id = pec_id;
+                    } else {
+                        uint32_t m4[4], key = 0;
+                        int q = 0;
+                        for (int d2 = -1; d2 <= 0; ++d2)
+                            for (int d1 = -1; d1 <= 0; ++d1) {
                                 int c[3] = {i, j, k};
                                 c[a1] += d1;
                                 c[a2] += d2;
-                                const fdtd_material &m = mat(c[0], c[1], c[2]);
-                                if (m.is_pec) pec = true;
-                                se += m.eps_r;
-                                ss += m.sigma;
+                                m4[q] = cell(c[0], c[1], c[2]);
+                                key = (key << 8) | m4[q];
+                                ++q;
                             }
+                        id = key == last_key ? last_id : coef_id(key, m4);
+                        last_key = key;
+                        last_id = id;
                     }
-                    double ca = 0, cb = 0;
-                    if (!pec) {
-                        const double eps = P.eps0 * (se / 4.0);
-                        const double sig = ss / 4.0;
-                        const double half_loss = sig * P.dt / (2.0 * eps);
-                        ca = (1.0 - half_loss) / (1.0 + half_loss);
-                        cb = (P.dt / eps) / (1.0 + half_loss);
-                    }
-                    const int id = lookup(ca, cb);
                     P.ids[comp][(size_t)i + (size_t)P.px * ((size_t)j + (size_t)ny * k)] =
                         (uint16_t)std::min(id, 65535);
                 }
+            }
     }
     REQUIRE(table.size() <= 65536, FDTD_E_UNSUPPORTED,
             "more than 65536 distinct edge coefficients");
@@ -236,6 +266,7 @@ static void layout(Plan &P)
     take(P.r_tw, std::max<size_t>(1, P.tw.size()) * 8);
     take(P.r_range, std::max<size_t>(1, P.prange.size()) * 4);
     take(P.r_freq, std::max<size_t>(1, P.freqs.size()) * 8);
+    take(P.r_grid, GRID_PROBES_OFF + sizeof(DevProbes) + 64);
     P.r_static.bytes = cur;
     // mutable state
     P.r_mut.off = cur;
@@ -280,6 +311,9 @@ static void finalize(Plan &P)
     }
     P.elt = g.precision == FDTD_FP64 ? 8 : 4;
     P.nbuf = g.kernel == FDTD_KERNEL_FUSED ? 2 : 1;
+    // the fused kernel addresses every array with 32-bit byte offsets
+    REQUIRE(g.kernel != FDTD_KERNEL_FUSED || P.field_elems * 4 < ((size_t)1 << 32),
+            FDTD_E_UNSUPPORTED, "grid too large for one fused plan (field array >= 4 GiB)");
     const size_t Lx = P.lo[0] + P.hi[0], Ly = P.lo[1] + P.hi[1], Lz = P.lo[2] + P.hi[2];
     const size_t xl = Lx * g.ny * g.nz, yl = (size_t)P.px * Ly * g.nz,
                  zl = (size_t)P.px * g.ny * Lz;
@@ -313,6 +347,7 @@ DevGrid<T> Plan::dev_grid() const
     d.off = 64 + (int64_t)px * (1 + py);
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz; d.px = px; d.py = py;
     d.id16 = id16;
+    d.nlut = (int32_t)(lut[0].size() / 4);
     for (int a = 0; a < 3; ++a) { d.lo[a] = lo[a]; d.hi[a] = hi[a]; }
     d.ch[0] = (T)(dt / (mu0 * g.dx));
     d.ch[1] = (T)(dt / (mu0 * g.dy));
@@ -408,10 +443,27 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     upload(P, P.r_tw, P.tw.data(), P.tw.size() * 8, s);
     upload(P, P.r_range, P.prange.data(), P.prange.size() * 4, s);
     upload(P, P.r_freq, P.freqs.data(), P.freqs.size() * 8, s);
+    if (P.g.kernel == FDTD_KERNEL_FUSED) {
+        // launch table of the fused kernel: the descriptors of both buffer
+        // parities, the first block of the only instance (0) and the probes
+        DevGrid<float> g2[2];
+        const int par = P.parity;
+        for (int q = 0; q < 2; ++q) {
+            P.parity = q;
+            g2[q] = P.dev_grid<float>();
+        }
+        P.parity = par;
+        const DevProbes pr = dev_probes(P);
+        keep.emplace_back(P.r_grid.bytes, 0);
+        std::memcpy(keep.back().data(), g2, sizeof g2);
+        std::memcpy(keep.back().data() + GRID_PROBES_OFF, &pr, sizeof pr);
+        upload(P, P.r_grid, keep.back().data(), P.r_grid.bytes, s);
+    }
     hip_check(hipMemsetAsync(P.base + P.r_mut.off, 0, P.r_mut.bytes, s), "clear state");
     hip_check(hipStreamSynchronize(s), "bind sync");
     P.step = 0;
     P.dft_n = 0;
+    P.sampled = 0;
     P.parity = 0;
     P.bound = true;
 }
@@ -422,14 +474,16 @@ static void reset_plan(Plan &P, hipStream_t s)
     hip_check(hipMemsetAsync(P.base + P.r_mut.off, 0, P.r_mut.bytes, s), "reset");
     P.step = 0;
     P.dft_n = 0;
+    P.sampled = 0;
     P.parity = 0;
 }
 
+// Fold the samples dft_n+1 .. sampled of the history ring into the DFTs.
 static void flush_dft(Plan &P, hipStream_t s)
 {
-    if (P.step > P.dft_n) {
-        hip_check(launch_dft(dev_dft(P), P.dft_n + 1, P.step - P.dft_n, s), "dft");
-        P.dft_n = P.step;
+    if (P.sampled > P.dft_n) {
+        hip_check(launch_dft(dev_dft(P), P.dft_n + 1, P.sampled - P.dft_n, s), "dft");
+        P.dft_n = P.sampled;
     }
 }
 
@@ -502,25 +556,41 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
     REQUIRE(!P.in_batch, FDTD_E_STATE, "plan belongs to a batch; use fdtd_batch_run");
     REQUIRE(nsteps >= 0, FDTD_E_INVALID_ARG, "negative step count");
     const DevProbes pr = dev_probes(P);
+    const bool fused = P.g.kernel == FDTD_KERNEL_FUSED;
     for (int64_t t = 0; t < nsteps; ++t) {
         hipEvent_t e0, e1;
         hip_check(P.timer.slot(e0, e1), "timer");
-        if (P.g.kernel == FDTD_KERNEL_FUSED) {
-            const DevGrid<float> d = P.dev_grid<float>();
-            hip_check(launch_fused_step(d, P.cfg, P.step, s, e0, e1), "fused step");
+        if (fused) {
+            // the launch samples its input level P.step (if >= 1) as well
+            const char *tab = P.base + P.r_grid.off;
+            hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
+                                   reinterpret_cast<const int32_t *>(tab + GRID_START_OFF), 1,
+                                   fused_tiles(P.g.nx, P.g.ny, P.g.nz, P.cfg), P.cfg, P.step,
+                                   reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
+                                   P.nprobe(), P.nprobe() > 0, s, e0, e1),
+                      "fused step");
             P.parity = 1 - P.parity;
-            hip_check(launch_probe(P.dev_grid<float>(), pr, P.step + 1, s), "probe");
+            if (P.nprobe() > 0 && P.step >= 1) P.sampled = std::max(P.sampled, P.step);
         } else if (P.g.precision == FDTD_FP64) {
             const DevGrid<double> d = P.dev_grid<double>();
             hip_check(launch_plain_step(d, P.step, s, e0, e1), "plain step");
             hip_check(launch_probe(d, pr, P.step + 1, s), "probe");
+            P.sampled = P.step + 1;
         } else {
             const DevGrid<float> d = P.dev_grid<float>();
             hip_check(launch_plain_step(d, P.step, s, e0, e1), "plain step");
             hip_check(launch_probe(d, pr, P.step + 1, s), "probe");
+            P.sampled = P.step + 1;
         }
         P.step += 1;
-        if (P.step - P.dft_n >= P.K) flush_dft(P, s);
+        // the ring holds K samples: fold them in before the next one would
+        // overwrite an unfolded slot
+        if (P.sampled - P.dft_n >= P.K - 1) flush_dft(P, s);
+    }
+    if (fused && P.sampled < P.step) {
+        // the last level of the run has not been sampled by a launch yet
+        hip_check(launch_probe(P.dev_grid<float>(), pr, P.step, s), "probe");
+        P.sampled = P.step;
     }
     flush_dft(P, s);
 }
@@ -812,7 +882,7 @@ fdtd_status fdtd_write_field(fdtd_plan *plan, int32_t comp, const double *host, 
 
 struct CkHeader {
     uint64_t magic, mut_bytes;
-    int64_t step, dft_n;
+    int64_t step, dft_n, sampled;
     int32_t parity, pad;
 };
 static const uint64_t CK_MAGIC = 0x46445444434b5031ull;
@@ -833,7 +903,7 @@ fdtd_status fdtd_checkpoint_save(fdtd_plan *plan, void *host, size_t bytes, void
         REQUIRE(host, FDTD_E_INVALID_ARG, "null buffer");
         REQUIRE(bytes >= sizeof(CkHeader) + P.r_mut.bytes, FDTD_E_NOMEM, "checkpoint buffer too small");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        CkHeader h{CK_MAGIC, P.r_mut.bytes, P.step, P.dft_n, P.parity, 0};
+        CkHeader h{CK_MAGIC, P.r_mut.bytes, P.step, P.dft_n, P.sampled, P.parity, 0};
         std::memcpy(host, &h, sizeof h);
         hip_check(hipMemcpyAsync(static_cast<char *>(host) + sizeof h, P.base + P.r_mut.off,
                                  P.r_mut.bytes, hipMemcpyDeviceToHost, s), "checkpoint copy");
@@ -858,6 +928,7 @@ fdtd_status fdtd_checkpoint_load(fdtd_plan *plan, const void *host, size_t bytes
         hip_check(hipStreamSynchronize(s), "checkpoint sync");
         P.step = h.step;
         P.dft_n = h.dft_n;
+        P.sampled = h.sampled;
         P.parity = h.parity;
     });
 }
@@ -873,9 +944,9 @@ fdtd_status fdtd_plan_get_config(const fdtd_plan *plan, int32_t *rows, int32_t *
 fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t rows, int32_t zchunk)
 {
     PLAN_GUARD(plan) {
-        REQUIRE(rows == 1 || rows == 2 || rows == 4 || rows == 8 || rows == 16,
-                FDTD_E_INVALID_ARG, "tile rows must be 1, 2, 4, 8 or 16");
-        REQUIRE(zchunk >= 1, FDTD_E_INVALID_ARG, "z-chunk must be positive");
+        REQUIRE(rows == 2 || rows == 4 || rows == 8 || rows == 16,
+                FDTD_E_INVALID_ARG, "tile rows must be 2, 4, 8 or 16");
+        REQUIRE(zchunk >= 1 && zchunk <= 64, FDTD_E_INVALID_ARG, "z-chunk must be in [1, 64]");
         plan->cfg.rows = rows;
         plan->cfg.zchunk = zchunk;
     });

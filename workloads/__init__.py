@@ -279,6 +279,92 @@ def geometry_sweep(nsteps: int = 50000, shapes=None) -> List[Problem]:
     return out
 
 
+def paper_microstrip(nsteps: int = 60000, nf: int = 60, pml: int = 10, strip_cells: int = 1,
+                     ports=(100, 900), src_i: int = 40) -> Problem:
+    """The verification line of the paper's Sec. II-B, with x as the
+    propagation axis: 1000 (x) by 200 (y) by 50 (z) cells of 0.1 mm, oxide
+    (eps_r 3.8) 1 mm thick (10 cells) on a PEC ground, a PEC strip 5.7 mm
+    (57 cells) wide along the whole line, CFL 0.9, differential Gaussian
+    sigma = 11.254 ps (t0 = 3 sigma), 60 000 steps, absorbing layers on the
+    other five faces.  The strip thickness and the port positions are not
+    given in the paper: one cell and ports 800 cells apart."""
+    nx, ny, nz = 1000, 200, 50
+    h, w = 10, 57
+    y0 = (ny - w) // 2
+    y1 = y0 + w
+    mats = [Material(1.0), Material(3.8), Material(1.0, pec=True)]
+    cells = np.zeros((nz, ny, nx), dtype=np.uint8)
+    cells[:h] = 1
+    cells[h:h + strip_cells, y0:y1, :] = 2
+    src = Source(DIFF_GAUSSIAN, (src_i, src_i, y0, y1, 0, h - 1), width=11.254e-12)
+    plist = [Port(ports[0], +1, y0, y1, h, h + strip_cells),
+             Port(ports[1], -1, y0, y1, h, h + strip_cells)]
+    return Problem(
+        name="paper_microstrip_1000x200x50", nx=nx, ny=ny, nz=nz, dx=1e-4, dy=1e-4, dz=1e-4,
+        courant=0.9, normalized=False, materials=mats, cells=cells,
+        faces=(CPML, CPML, CPML, CPML, PEC, CPML), pml_cells=(pml,) * 6, source=src,
+        ports=plist, freqs=linear_freqs(0.5e9, 60e9, nf), nsteps=nsteps, fp32=True)
+
+
+# ---------------------------------------------------------------------------
+# Non-uniform 2-port: the four runs of the incident/total protocol
+# ---------------------------------------------------------------------------
+
+def step_circuit(nx=400, ny=120, nz=80, delta=5e-9, w1=8, w2=16, step_x=200, sub_top=20,
+                 strip_t=2, pml=10, src_margin=20, port_margin=60, nsteps=20000, nf=64,
+                 twin=True, fp32=True, z_step=0):
+    """A microstrip whose strip changes width (w1 -> w2 cells) and, with
+    ``z_step`` > 0, also rises by that many cells at x = ``step_x``.
+
+    Returns the runs of the per-port protocol as a dict:
+      inc1 / inc2: a uniform line with port 1's / port 2's cross-section,
+                   driven next to that port (no internal reflections);
+      tot1 / tot2: the full circuit driven next to port 1 / port 2.
+    Every run carries both ports (port 1 at x = port_margin, inward +x;
+    port 2 at x = nx - port_margin, inward -x)."""
+    s = 1e3 if twin else 1.0
+    band = (10e9 * s, 300e9 * s)
+    mats = [Material(1.0), Material(11.7), Material(1.0, pec=True)]
+
+    def strip_box(w, zlift):
+        y0 = (ny - w) // 2
+        return y0, y0 + w, sub_top + zlift, sub_top + zlift + strip_t
+
+    b1, b2 = strip_box(w1, 0), strip_box(w2, z_step)
+
+    def cells_for(kind):
+        c = np.zeros((nz, ny, nx), dtype=np.uint8)
+        c[:sub_top] = 1
+        if kind == "uniform1":
+            c[b1[2]:b1[3], b1[0]:b1[1], :] = 2
+        elif kind == "uniform2":
+            c[:sub_top + z_step] = 1
+            c[b2[2]:b2[3], b2[0]:b2[1], :] = 2
+        else:
+            c[b1[2]:b1[3], b1[0]:b1[1], :step_x] = 2
+            c[sub_top:sub_top + z_step, :, step_x:] = 1
+            c[b2[2]:b2[3], b2[0]:b2[1], step_x:] = 2
+        return c
+
+    ports = [Port(port_margin, +1, b1[0], b1[1], b1[2], b1[3]),
+             Port(nx - port_margin, -1, b2[0], b2[1], b2[2], b2[3])]
+    src1 = Source(GAUSS_SINE, (src_margin, src_margin, b1[0], b1[1], 0, b1[2] - 1),
+                  fc=150e9 * s, bandwidth=300e9 * s)
+    src2 = Source(GAUSS_SINE, (nx - src_margin, nx - src_margin, b2[0], b2[1], 0, b2[2] - 1),
+                  fc=150e9 * s, bandwidth=300e9 * s)
+
+    def prob(name, kind, src):
+        return Problem(name=f"step_{name}_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, dx=delta,
+                       dy=delta, dz=delta, courant=0.99, normalized=False,
+                       materials=[Material(m.eps_r, m.sigma, m.pec) for m in mats],
+                       cells=cells_for(kind), faces=(CPML, CPML, CPML, CPML, PEC, CPML),
+                       pml_cells=(pml,) * 6, source=src, ports=list(ports),
+                       freqs=linear_freqs(band[0], band[1], nf), nsteps=nsteps, fp32=fp32)
+
+    return {"inc1": prob("inc1", "uniform1", src1), "tot1": prob("tot1", "step", src1),
+            "inc2": prob("inc2", "uniform2", src2), "tot2": prob("tot2", "step", src2)}
+
+
 # ---------------------------------------------------------------------------
 # Test-only geometries
 # ---------------------------------------------------------------------------
