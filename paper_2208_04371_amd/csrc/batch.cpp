@@ -66,9 +66,9 @@ fdtd_status bguard(Batch *b, F &&f)
 }
 
 // Device tables of a bound batch (offsets inside its workspace):
-// [grids parity 0][grids parity 1][block_start][probes][dft]
+// [grids parity 0][grids parity 1][tile sets][probes][dft]
 struct Tables {
-    size_t grids[2], starts, probes, dft, bytes;
+    size_t grids[2], sets, probes, dft, bytes;
 };
 
 Tables table_layout(int n)
@@ -77,7 +77,7 @@ Tables table_layout(int n)
     size_t cur = 0;
     t.grids[0] = cur; cur = al256(cur + sizeof(DevGrid<float>) * n);
     t.grids[1] = cur; cur = al256(cur + sizeof(DevGrid<float>) * n);
-    t.starts = cur; cur = al256(cur + sizeof(int32_t) * n);
+    t.sets = cur; cur = al256(cur + sizeof(TileSet) * n);
     t.probes = cur; cur = al256(cur + sizeof(DevProbes) * n);
     t.dft = cur; cur = al256(cur + sizeof(DevDft) * n);
     t.bytes = cur;
@@ -86,14 +86,18 @@ Tables table_layout(int n)
 
 void compute_blocks(Batch &B)
 {
-    B.block_start.assign(B.plans.size(), 0);
-    int32_t total = 0;
+    B.sets.assign(B.plans.size(), TileSet{});
+    int32_t nb = 0, ni = 0;
     for (size_t q = 0; q < B.plans.size(); ++q) {
-        B.block_start[q] = total;
-        const Plan &P = *B.plans[q];
-        total += fused_tiles(P.g.nx, P.g.ny, P.g.nz, B.cfg);
+        TileSet &t = B.sets[q];
+        t = make_tileset(*B.plans[q], B.cfg);
+        t.sb = nb;
+        t.si = ni;
+        nb += t.nb;
+        ni += t.ni;
     }
-    B.total_blocks = total;
+    B.nb_total = nb;
+    B.ni_total = ni;
 }
 
 // Upload the instance tables for the current parity of the member plans.
@@ -119,7 +123,7 @@ void upload_tables(Batch &B, hipStream_t s)
     char *base = B.base + B.r_table.off;
     hcheck(hipMemcpyAsync(base + t.grids[0], g0.data(), sizeof(DevGrid<float>) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.grids[1], g1.data(), sizeof(DevGrid<float>) * n, hipMemcpyHostToDevice, s), "table");
-    hcheck(hipMemcpyAsync(base + t.starts, B.block_start.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipMemcpyAsync(base + t.sets, B.sets.data(), sizeof(TileSet) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.probes, pr.data(), sizeof(DevProbes) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.dft, df.data(), sizeof(DevDft) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipStreamSynchronize(s), "table sync");
@@ -146,7 +150,7 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
     const int n = (int)B.plans.size();
     const Tables t = table_layout(n);
     char *tb = B.base + B.r_table.off;
-    const int32_t *starts = reinterpret_cast<const int32_t *>(tb + t.starts);
+    const TileSet *sets = reinterpret_cast<const TileSet *>(tb + t.sets);
     const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes);
     Plan &P0 = *B.plans[0];
     const bool sample = B.max_probes > 0;
@@ -154,9 +158,9 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
         const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
         hipEvent_t e0, e1;
         hcheck(B.timer.slot(e0, e1), "timer");
-        // one launch: every instance's step, plus sampling of its input level
-        hcheck(launch_fused(g, starts, n, B.total_blocks, B.cfg, P0.step, probes, B.max_probes,
-                            sample, s, e0, e1),
+        // every instance's step, plus sampling of its input level
+        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, P0.step, probes,
+                            B.max_probes, sample, s, e0, e1),
                "batch step");
         const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
         for (Plan *P : B.plans) {

@@ -29,7 +29,7 @@ namespace fdtd {
 namespace {
 
 constexpr int TW = 64;        // tile width in x = one wavefront
-constexpr int LUT_LDS = 64;   // LUTs up to this many entries live in LDS
+constexpr int LUT_LDS = 256;  // coefficient sets per component (8-bit ids)
 
 // Block barrier that orders LDS accesses only: outstanding global loads
 // (the prefetch of the next plane) stay in flight.
@@ -164,130 +164,151 @@ struct Smem {
     float e[3][3][R + 2][TW + 2];   // 3 rotating E^n planes: rows y0-1..y0+R, cols x0-1..x0+64
     float h[3][R + 1][TW + 1];      // H^{n+1/2}(k): rows y0-1..y0+R-1, cols x0-1..x0+63
     float4 lut[3][LUT_LDS];
-    float px[PR_COUNT][TW + 2];     // x profiles at x0-1 .. x0+64
+    float px[PR_COUNT][TW + 2];     // x profiles at x0-1 .. x0+64 (boundary tiles)
     float py[PR_COUNT][R + 2];      // y profiles at y0-1 .. y0+R
     float pz[PR_COUNT][ZMAX + 1];   // z profiles at z0-1 .. z0+ZMAX-1
+    float dummy[TW];                // target of the writes of repeated items
 };
 
 // H^{n+1/2} from H^{n-1/2} and the six forward differences of E^n at the
-// LDS-cache positions (lx, ly, lz) of the block.  With `store` the updated
-// auxiliaries of the H components are written.
-template <int R>
+// LDS-cache positions (lx, ly, lz) of the block.  Inside the layers (LAYERS
+// kernels only) the differences take their auxiliaries; with `store` the
+// updated auxiliaries of the H components are written.
+template <int R, bool LAYERS>
 __device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Smem<R> &sm,
                                         const LayerPos &L, int lx, int ly, int lz, HDiff df,
                                         const Psi6 &ps, bool store, float hx, float hy, float hz,
                                         float &ox, float &oy, float &oz)
 {
-    float pn;
-    if (L.inx) {
-        const float b = sm.px[PR_BH][lx], c = sm.px[PR_CH][lx], ik = sm.px[PR_KH][lx];
-        df.ez_x = lterm(df.ez_x, b, c, ik, ps.v[PSI_HYX], pn);
-        if (store) stf(d.psi_o[PSI_HYX], L.qx, pn);
-        df.ey_x = lterm(df.ey_x, b, c, ik, ps.v[PSI_HZX], pn);
-        if (store) stf(d.psi_o[PSI_HZX], L.qx, pn);
-    }
-    if (L.iny) {
-        const float b = sm.py[PR_BH][ly], c = sm.py[PR_CH][ly], ik = sm.py[PR_KH][ly];
-        df.ez_y = lterm(df.ez_y, b, c, ik, ps.v[PSI_HXY], pn);
-        if (store) stf(d.psi_o[PSI_HXY], L.qy, pn);
-        df.ex_y = lterm(df.ex_y, b, c, ik, ps.v[PSI_HZY], pn);
-        if (store) stf(d.psi_o[PSI_HZY], L.qy, pn);
-    }
-    if (L.inz) {
-        const float b = sm.pz[PR_BH][lz], c = sm.pz[PR_CH][lz], ik = sm.pz[PR_KH][lz];
-        df.ey_z = lterm(df.ey_z, b, c, ik, ps.v[PSI_HXZ], pn);
-        if (store) stf(d.psi_o[PSI_HXZ], L.qz, pn);
-        df.ex_z = lterm(df.ex_z, b, c, ik, ps.v[PSI_HYZ], pn);
-        if (store) stf(d.psi_o[PSI_HYZ], L.qz, pn);
+    if constexpr (LAYERS) {
+        float pn;
+        if (L.inx) {
+            const float b = sm.px[PR_BH][lx], c = sm.px[PR_CH][lx], ik = sm.px[PR_KH][lx];
+            df.ez_x = lterm(df.ez_x, b, c, ik, ps.v[PSI_HYX], pn);
+            if (store) stf(d.psi_o[PSI_HYX], L.qx, pn);
+            df.ey_x = lterm(df.ey_x, b, c, ik, ps.v[PSI_HZX], pn);
+            if (store) stf(d.psi_o[PSI_HZX], L.qx, pn);
+        }
+        if (L.iny) {
+            const float b = sm.py[PR_BH][ly], c = sm.py[PR_CH][ly], ik = sm.py[PR_KH][ly];
+            df.ez_y = lterm(df.ez_y, b, c, ik, ps.v[PSI_HXY], pn);
+            if (store) stf(d.psi_o[PSI_HXY], L.qy, pn);
+            df.ex_y = lterm(df.ex_y, b, c, ik, ps.v[PSI_HZY], pn);
+            if (store) stf(d.psi_o[PSI_HZY], L.qy, pn);
+        }
+        if (L.inz) {
+            const float b = sm.pz[PR_BH][lz], c = sm.pz[PR_CH][lz], ik = sm.pz[PR_KH][lz];
+            df.ey_z = lterm(df.ey_z, b, c, ik, ps.v[PSI_HXZ], pn);
+            if (store) stf(d.psi_o[PSI_HXZ], L.qz, pn);
+            df.ex_z = lterm(df.ex_z, b, c, ik, ps.v[PSI_HYZ], pn);
+            if (store) stf(d.psi_o[PSI_HYZ], L.qz, pn);
+        }
     }
     ox = hx - d.ch[1] * df.ez_y + d.ch[2] * df.ey_z;
     oy = hy - d.ch[2] * df.ex_z + d.ch[0] * df.ez_x;
     oz = hz - d.ch[0] * df.ey_x + d.ch[1] * df.ex_y;
 }
 
-// Rows of the E patch a wave loads: R waves share the R+2 rows of each
-// component; halo columns x0-1 and x0+64 are loaded by the first threads.
+// The E^n patch of one plane: rows y0-1 .. y0+R (R+2) of the three
+// components over columns x0 .. x0+63, and the halo columns x0-1, x0+64.
+// Wave w loads row w of each component (rows 0..R-1), NX more row loads
+// from the six remaining (component, row R or R+1) items, and one halo
+// value per lane.  Every wave issues the same loads: items past the last
+// repeat it and land in a dummy LDS row, so no load sits behind a branch
+// (a branch around a load makes the compiler wait for every load and store
+// in flight).
 template <int R>
 struct EPatch {
-    static constexpr int Q = (R + 2 + R - 1) / R;   // rows per wave and component
-    float v[3][Q];
+    static constexpr int NX = (6 + R - 1) / R;       // extra row loads per wave
+    static constexpr int NHALO = 6 * (R + 2);        // 2 sides x 3 comps x rows
+    float v[3];
+    float x[NX];
     float halo;
 };
 
-template <int R>
-__device__ __forceinline__ void epatch_load(const DevGrid<float> &d, EPatch<R> &p, int x0, int y0,
-                                            int k)
+__device__ __forceinline__ const float *comp_ptr(const float *c0, int64_t stride, int c)
 {
-    const int t = threadIdx.x, lane = t & (TW - 1), w = t / TW;
-    const uint32_t base = (uint32_t)(d.off + x0 + d.px * (y0 - 1) + d.px * d.py * k);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int q = 0; q < EPatch<R>::Q; ++q) {
-            const int row = w + R * q;
-            if (row < R + 2) p.v[c][q] = ldf(d.E[c], base + d.px * row + lane);
-        }
-    // halo columns: thread t -> side t & 1, component and row from t >> 1
-    if (t < 6 * (R + 2)) {
-        const int side = t & 1, rest = t >> 1;
-        const int c = rest / (R + 2), row = rest % (R + 2);
-        const uint32_t a = base + d.px * row + (side ? TW : 0) - (side ? 0 : 1);
-        p.halo = ldf(c == 0 ? d.E[0] : (c == 1 ? d.E[1] : d.E[2]), a);
-    }
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(c0) + c * stride);
 }
 
 template <int R>
-__device__ __forceinline__ void epatch_store(Smem<R> &sm, const EPatch<R> &p, int slot)
+__device__ __forceinline__ void epatch_load(const DevGrid<float> &d, EPatch<R> &p, int x0, int y0,
+                                            int k, int w)
 {
-    const int t = threadIdx.x, lane = t & (TW - 1), w = t / TW;
+    const int t = threadIdx.x, lane = t & (TW - 1);
+    const uint32_t base = (uint32_t)(d.off + x0 + d.px * (y0 - 1) + d.px * d.py * k);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) p.v[c] = ldf(d.E[c], base + d.px * w + lane);
 #pragma unroll
-        for (int q = 0; q < EPatch<R>::Q; ++q) {
-            const int row = w + R * q;
-            if (row < R + 2) sm.e[slot][c][row][lane + 1] = p.v[c][q];
-        }
-    if (t < 6 * (R + 2)) {
-        const int side = t & 1, rest = t >> 1;
-        const int c = rest / (R + 2), row = rest % (R + 2);
-        sm.e[slot][c][row][side ? TW + 1 : 0] = p.halo;
+    for (int q = 0; q < EPatch<R>::NX; ++q) {
+        const int e = min(w * EPatch<R>::NX + q, 5);          // uniform per wave
+        p.x[q] = ldf(comp_ptr(d.E[0], d.cstride, e >> 1), base + d.px * (R + (e & 1)) + lane);
     }
+    const int tt = min(t, EPatch<R>::NHALO - 1);
+    const int side = tt & 1, rest = tt >> 1;
+    const int c = rest / (R + 2), row = rest % (R + 2);
+    p.halo = ldf(comp_ptr(d.E[0], d.cstride, c), base + d.px * row + (side ? TW : 0) - (side ? 0 : 1));
+}
+
+template <int R>
+__device__ __forceinline__ void epatch_store(Smem<R> &sm, const EPatch<R> &p, int slot, int w)
+{
+    const int t = threadIdx.x, lane = t & (TW - 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sm.e[slot][c][w][lane + 1] = p.v[c];
+#pragma unroll
+    for (int q = 0; q < EPatch<R>::NX; ++q) {
+        const int e = w * EPatch<R>::NX + q;
+        float *dst = e < 6 ? &sm.e[slot][e >> 1][R + (e & 1)][lane + 1] : &sm.dummy[lane];
+        *dst = p.x[q];
+    }
+    const int side = t & 1, rest = t >> 1;
+    const int c = rest / (R + 2), row = rest % (R + 2);
+    float *dst = t < EPatch<R>::NHALO ? &sm.e[slot][c][row][side ? TW + 1 : 0] : &sm.dummy[lane];
+    *dst = p.halo;
 }
 
 // What plane k of the own cell (and the halo cell of this thread) needs
 // from HBM besides the E patch; loaded one plane ahead.
 struct PlaneRegs {
     float hx, hy, hz;          // H^{n-1/2} own
-    int idx, idy, idz;         // edge ids own
+    uint32_t ids;              // edge ids own (x, y, z in bytes 0, 1, 2)
     float hhx, hhy, hhz;       // H^{n-1/2} of the halo cell
-    Psi6 ph;                   // H auxiliaries of the own cell
+    Psi6 ph;                   // H auxiliaries of the own cell (boundary tiles)
 };
 
-__device__ __forceinline__ void plane_load(const DevGrid<float> &d, PlaneRegs &r, bool own, int i,
-                                           int j, int k, bool has_halo, int hi_, int hj_)
+// Per-thread constants of one tile.
+struct TileCtx {
+    int x0, y0, z0, z1;
+    int w;                     // wave index (uniform)
+    int i, j, lx, ly;          // own cell and its LDS position
+    int ci, cj;                // own cell clamped into the grid (load address)
+    int hi_, hj_, hlx, hly;    // halo cell and its LDS position
+    int chi, chj;              // halo cell clamped into the grid (load address)
+    bool own, halo_thread, halo_live, src_col;
+    float sval;                // source value of the output level
+    uint32_t sy, sz;           // field strides
+};
+
+// Loads for plane k: unconditional (lanes without a cell load a clamped
+// one and discard it); only the auxiliaries of boundary tiles depend on the
+// lane.
+template <bool LAYERS>
+__device__ __forceinline__ void plane_load(const DevGrid<float> &d, PlaneRegs &r, const TileCtx &t,
+                                           int k)
 {
-    if (own) {
-        const uint32_t c = (uint32_t)(d.off + i + d.px * j + d.px * d.py * k);
-        r.hx = ldf(d.H[0], c);
-        r.hy = ldf(d.H[1], c);
-        r.hz = ldf(d.H[2], c);
-        const uint32_t qi = (uint32_t)(i + d.px * (j + d.ny * k));
-        if (d.id16) {
-            r.idx = gld(static_cast<const uint16_t *>(d.ids[0]), qi);
-            r.idy = gld(static_cast<const uint16_t *>(d.ids[1]), qi);
-            r.idz = gld(static_cast<const uint16_t *>(d.ids[2]), qi);
-        } else {
-            r.idx = gld(static_cast<const uint8_t *>(d.ids[0]), qi);
-            r.idy = gld(static_cast<const uint8_t *>(d.ids[1]), qi);
-            r.idz = gld(static_cast<const uint8_t *>(d.ids[2]), qi);
-        }
-        load_psi_h(d, layer_pos(d, i, j, k), r.ph);
-    }
-    if (has_halo) {
-        const uint32_t c = (uint32_t)(d.off + hi_ + d.px * hj_ + d.px * d.py * k);
-        r.hhx = ldf(d.H[0], c);
-        r.hhy = ldf(d.H[1], c);
-        r.hhz = ldf(d.H[2], c);
+    const uint32_t c = (uint32_t)(d.off + t.ci) + t.sy * t.cj + t.sz * k;
+    r.hx = ldf(d.H[0], c);
+    r.hy = ldf(d.H[1], c);
+    r.hz = ldf(d.H[2], c);
+    r.ids = gld(static_cast<const uint32_t *>(d.ids[0]),
+                (uint32_t)(t.ci + d.px * (t.cj + d.ny * k)));
+    const uint32_t h = (uint32_t)(d.off + t.chi) + t.sy * t.chj + t.sz * k;
+    r.hhx = ldf(d.H[0], h);
+    r.hhy = ldf(d.H[1], h);
+    r.hhz = ldf(d.H[2], h);
+    if constexpr (LAYERS) {
+        if (t.own) load_psi_h(d, layer_pos(d, t.i, t.j, k), r.ph);
     }
 }
 
@@ -298,219 +319,270 @@ __device__ __forceinline__ float prof_at(const float *prof, int tab, int n, int 
     return (p >= 0 && p < n) ? gld(prof, (uint32_t)(tab * n + p)) : 0.f;
 }
 
-template <int R>
-__device__ void fused_tile(const DevGrid<float> &d, int tile, int zchunk, int64_t level,
-                           Smem<R> &sm)
+// Rotating state of the march through the planes.
+struct MarchState {
+    int s0, s1, s2;            // LDS slots of E^n planes k, k+1, k+2
+    float hx_prev, hy_prev;    // H^{n+1/2}(k-1) of the own cell
+};
+
+// One plane k (< z1) of the march.  `cur` holds what plane k needs from
+// HBM (loaded during plane k-1); `nxt` receives what plane k+1 needs.  The
+// caller alternates the two register sets instead of copying them: a copy
+// would have to wait for the loads in flight.  Past the end of the chunk
+// the prefetches repeat the last plane (cache hits, results unused).
+template <int R, bool LAYERS>
+__device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm, const TileCtx &t,
+                                            int k, const PlaneRegs &cur, PlaneRegs &nxt,
+                                            MarchState &m)
 {
-    const int tiles_x = (d.nx + TW - 1) / TW, tiles_y = (d.ny + R - 1) / R;
-    const int tx = tile % tiles_x;
-    const int ty = (tile / tiles_x) % tiles_y;
-    const int tz = tile / (tiles_x * tiles_y);
-    const int x0 = tx * TW, y0 = ty * R, z0 = tz * zchunk;
-    const int z1 = min(z0 + zchunk, d.nz);
+    const int lx = t.lx, ly = t.ly, hlx = t.hlx, hly = t.hly, lane = threadIdx.x & (TW - 1);
+    const int s0 = m.s0, s1 = m.s1, s2 = m.s2;
+    const int lz = k - t.z0 + 1;
+    // ---- requests: this plane's auxiliaries (boundary tiles), then
+    //      everything plane k+1 needs (consumed one plane later) -------------
+    LayerPos L{}, Lh{};
+    Psi6 pe_cur{}, ph_halo{};
+    if constexpr (LAYERS) {
+        L = layer_pos(d, t.i, t.j, k);
+        if (t.own) load_psi_e(d, L, pe_cur);
+        if (t.halo_live) {
+            Lh = layer_pos(d, t.hi_, t.hj_, k);
+            load_psi_h(d, Lh, ph_halo);
+        }
+    }
+    EPatch<R> pe;
+    epatch_load<R>(d, pe, t.x0, t.y0, min(k + 2, t.z1), t.w);
+    plane_load<LAYERS>(d, nxt, t, min(k + 1, t.z1 - 1));
+
+    // lanes without a cell store into the sink
+    const uint32_t c = t.own ? (uint32_t)(d.off + t.i) + t.sy * t.j + t.sz * k
+                             : (uint32_t)d.sink + (uint32_t)lane;
+    // ---- H^{n+1/2}(k): own cell -------------------------------------------
+    {
+        HDiff df;
+        const float ex = sm.e[s0][0][ly][lx], ey = sm.e[s0][1][ly][lx], ez = sm.e[s0][2][ly][lx];
+        df.ez_y = sm.e[s0][2][ly + 1][lx] - ez;
+        df.ey_z = sm.e[s1][1][ly][lx] - ey;
+        df.ex_z = sm.e[s1][0][ly][lx] - ex;
+        df.ez_x = sm.e[s0][2][ly][lx + 1] - ez;
+        df.ey_x = sm.e[s0][1][ly][lx + 1] - ey;
+        df.ex_y = sm.e[s0][0][ly + 1][lx] - ex;
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        if (!LAYERS || t.own)
+            h_apply<R, LAYERS>(d, sm, L, lx, ly, lz, df, cur.ph, true, cur.hx, cur.hy, cur.hz,
+                               ox, oy, oz);
+        stf(d.Ho[0], c, ox);
+        stf(d.Ho[1], c, oy);
+        stf(d.Ho[2], c, oz);
+        sm.h[0][ly][lx] = t.own ? ox : 0.f;
+        sm.h[1][ly][lx] = t.own ? oy : 0.f;
+        sm.h[2][ly][lx] = t.own ? oz : 0.f;
+    }
+    // ---- H^{n+1/2}(k): halo row y0-1 and halo column x0-1 -----------------
+    {
+        HDiff df;
+        const float ex = sm.e[s0][0][hly][hlx], ey = sm.e[s0][1][hly][hlx],
+                    ez = sm.e[s0][2][hly][hlx];
+        df.ez_y = sm.e[s0][2][hly + 1][hlx] - ez;
+        df.ey_z = sm.e[s1][1][hly][hlx] - ey;
+        df.ex_z = sm.e[s1][0][hly][hlx] - ex;
+        df.ez_x = sm.e[s0][2][hly][hlx + 1] - ez;
+        df.ey_x = sm.e[s0][1][hly][hlx + 1] - ey;
+        df.ex_y = sm.e[s0][0][hly + 1][hlx] - ex;
+        float ox, oy, oz;
+        h_apply<R, LAYERS>(d, sm, Lh, hlx, hly, lz, df, ph_halo, false, cur.hhx, cur.hhy,
+                           cur.hhz, ox, oy, oz);
+        // halo cells outside the grid only feed PEC edges: keep them zero
+        const bool live = t.halo_live;
+        float *hx = t.halo_thread ? &sm.h[0][hly][hlx] : &sm.dummy[lane];
+        float *hy = t.halo_thread ? &sm.h[1][hly][hlx] : &sm.dummy[lane];
+        float *hz = t.halo_thread ? &sm.h[2][hly][hlx] : &sm.dummy[lane];
+        *hx = live ? ox : 0.f;
+        *hy = live ? oy : 0.f;
+        *hz = live ? oz : 0.f;
+    }
+    lds_barrier();
+
+    // ---- E^{n+1}(k): own cell ---------------------------------------------
+    {
+        const float hx = sm.h[0][ly][lx], hy = sm.h[1][ly][lx], hz = sm.h[2][ly][lx];
+        float dHz_y = hz - sm.h[2][ly - 1][lx];
+        float dHy_z = hy - m.hy_prev;
+        float dHx_z = hx - m.hx_prev;
+        float dHz_x = hz - sm.h[2][ly][lx - 1];
+        float dHy_x = hy - sm.h[1][ly][lx - 1];
+        float dHx_y = hx - sm.h[0][ly - 1][lx];
+        if constexpr (LAYERS) {
+            if (t.own) {
+                float pn;
+                if (L.inx) {
+                    const float b = sm.px[PR_BE][lx], cc = sm.px[PR_CE][lx], ik = sm.px[PR_KE][lx];
+                    dHz_x = lterm(dHz_x, b, cc, ik, pe_cur.v[PSI_EYX - 6], pn);
+                    stf(d.psi_o[PSI_EYX], L.qx, pn);
+                    dHy_x = lterm(dHy_x, b, cc, ik, pe_cur.v[PSI_EZX - 6], pn);
+                    stf(d.psi_o[PSI_EZX], L.qx, pn);
+                }
+                if (L.iny) {
+                    const float b = sm.py[PR_BE][ly], cc = sm.py[PR_CE][ly], ik = sm.py[PR_KE][ly];
+                    dHz_y = lterm(dHz_y, b, cc, ik, pe_cur.v[PSI_EXY - 6], pn);
+                    stf(d.psi_o[PSI_EXY], L.qy, pn);
+                    dHx_y = lterm(dHx_y, b, cc, ik, pe_cur.v[PSI_EZY - 6], pn);
+                    stf(d.psi_o[PSI_EZY], L.qy, pn);
+                }
+                if (L.inz) {
+                    const float b = sm.pz[PR_BE][lz], cc = sm.pz[PR_CE][lz], ik = sm.pz[PR_KE][lz];
+                    dHy_z = lterm(dHy_z, b, cc, ik, pe_cur.v[PSI_EXZ - 6], pn);
+                    stf(d.psi_o[PSI_EXZ], L.qz, pn);
+                    dHx_z = lterm(dHx_z, b, cc, ik, pe_cur.v[PSI_EYZ - 6], pn);
+                    stf(d.psi_o[PSI_EYZ], L.qz, pn);
+                }
+            }
+        }
+        const float4 cx = sm.lut[0][cur.ids & 0xffu];
+        const float4 cy = sm.lut[1][(cur.ids >> 8) & 0xffu];
+        const float4 cz = sm.lut[2][(cur.ids >> 16) & 0xffu];
+        const float ex = cx.x * sm.e[s0][0][ly][lx] + cx.y * dHz_y - cx.z * dHy_z;
+        const float ey = cy.x * sm.e[s0][1][ly][lx] + cy.y * dHx_z - cy.z * dHz_x;
+        float ez = cz.x * sm.e[s0][2][ly][lx] + cz.y * dHy_x - cz.z * dHx_y;
+        if (t.src_col && k >= d.src_box[4] && k <= d.src_box[5]) ez += t.sval;
+        stf(d.Eo[0], c, ex);
+        stf(d.Eo[1], c, ey);
+        stf(d.Eo[2], c, ez);
+        m.hx_prev = hx;
+        m.hy_prev = hy;
+    }
+    // ---- rotate: plane k+2 into the LDS slot plane k leaves ----------------
+    epatch_store<R>(sm, pe, s2, t.w);
+    m.s0 = s1;
+    m.s1 = s2;
+    m.s2 = s0;
+    lds_barrier();
+}
+
+template <int R, bool LAYERS>
+__device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int zchunk,
+                           int64_t level, Smem<R> &sm)
+{
+    TileCtx tc;
+    tc.x0 = tx * TW;
+    tc.y0 = ty * R;
+    tc.z0 = tz * zchunk;
+    tc.z1 = min(tc.z0 + zchunk, d.nz);
+    const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0;
     const int t = threadIdx.x;
     const int lane = t & (TW - 1), row = t / TW;
+    tc.w = __builtin_amdgcn_readfirstlane(row);
     const int i = x0 + lane, j = y0 + row;
-    const bool own = i < d.nx && j < d.ny;
-    const int sy = d.px, sz = d.px * d.py;
-    const int lx = lane + 1, ly = row + 1;
+    tc.i = i;
+    tc.j = j;
+    tc.ci = min(i, d.nx - 1);
+    tc.cj = min(j, d.ny - 1);
+    tc.own = i < d.nx && j < d.ny;
+    tc.sy = (uint32_t)d.px;
+    tc.sz = (uint32_t)(d.px * d.py);
+    tc.lx = lane + 1;
+    tc.ly = row + 1;
+    const int lx = tc.lx, ly = tc.ly;
 
-    // the halo cell this thread recomputes H for (low-y row, then low-x column)
-    int hi_ = 0, hj_ = 0;
-    const bool halo_thread = t < TW + R + 1;
-    if (halo_thread) {
-        if (t < TW) { hi_ = x0 + t; hj_ = y0 - 1; }
-        else { hi_ = x0 - 1; hj_ = y0 - 1 + (t - TW); }
-    }
+    // the halo cell this thread recomputes H for: the low-y row, then the
+    // low-x column; the other threads repeat the last one (writing to a
+    // dummy LDS row) so that the halo work has no branch either
+    const int nh = TW + R + 1;
+    const int th = min(t, nh - 1);
+    const int hi_ = th < TW ? x0 + th : x0 - 1;
+    const int hj_ = th < TW ? y0 - 1 : y0 - 1 + (th - TW);
+    tc.halo_thread = t < nh;
     // only halo cells inside the grid matter: the others feed PEC edges only
-    const bool halo_live = halo_thread && hi_ >= 0 && hj_ >= 0 && hi_ < d.nx && hj_ < d.ny;
-    const int hlx = hi_ - x0 + 1, hly = hj_ - y0 + 1;
+    tc.halo_live = hi_ >= 0 && hj_ >= 0 && hi_ < d.nx && hj_ < d.ny;
+    tc.hi_ = hi_;
+    tc.hj_ = hj_;
+    tc.chi = max(min(hi_, d.nx - 1), 0);
+    tc.chj = max(min(hj_, d.ny - 1), 0);
+    tc.hlx = hi_ - x0 + 1;
+    tc.hly = hj_ - y0 + 1;
 
-    // ---- block caches: LUTs and the layer profiles of the tile ------------
+    // ---- block caches: LUTs (and the layer profiles of boundary tiles) ------
     const int nlut = d.nlut;
-    const bool lut_lds = nlut <= LUT_LDS;
-    if (lut_lds)
-        for (int q = t; q < 3 * nlut; q += TW * R) {
-            const int c = q / nlut, e = q % nlut;
-            sm.lut[c][e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
+    for (int q = t; q < 3 * nlut; q += TW * R) {
+        const int c = q / nlut, e = q % nlut;
+        sm.lut[c][e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
+    }
+    if constexpr (LAYERS) {
+        for (int q = t; q < PR_COUNT * (TW + 2); q += TW * R) {
+            const int tab = q / (TW + 2), p = q % (TW + 2);
+            sm.px[tab][p] = prof_at(d.prof[0], tab, d.nx, x0 - 1 + p);
         }
-    for (int q = t; q < PR_COUNT * (TW + 2); q += TW * R) {
-        const int tab = q / (TW + 2), p = q % (TW + 2);
-        sm.px[tab][p] = prof_at(d.prof[0], tab, d.nx, x0 - 1 + p);
-    }
-    for (int q = t; q < PR_COUNT * (R + 2); q += TW * R) {
-        const int tab = q / (R + 2), p = q % (R + 2);
-        sm.py[tab][p] = prof_at(d.prof[1], tab, d.ny, y0 - 1 + p);
-    }
-    for (int q = t; q < PR_COUNT * (ZMAX + 1); q += TW * R) {
-        const int tab = q / (ZMAX + 1), p = q % (ZMAX + 1);
-        sm.pz[tab][p] = prof_at(d.prof[2], tab, d.nz, z0 - 1 + p);
+        for (int q = t; q < PR_COUNT * (R + 2); q += TW * R) {
+            const int tab = q / (R + 2), p = q % (R + 2);
+            sm.py[tab][p] = prof_at(d.prof[1], tab, d.ny, y0 - 1 + p);
+        }
+        for (int q = t; q < PR_COUNT * (ZMAX + 1); q += TW * R) {
+            const int tab = q / (ZMAX + 1), p = q % (ZMAX + 1);
+            sm.pz[tab][p] = prof_at(d.prof[2], tab, d.nz, z0 - 1 + p);
+        }
     }
 
     // ---- prologue: request everything the first plane needs at once -------
     EPatch<R> pa, pb;
-    epatch_load<R>(d, pa, x0, y0, z0);
-    epatch_load<R>(d, pb, x0, y0, z0 + 1);
-    PlaneRegs cur_r{}, nxt_r{};
-    plane_load(d, cur_r, own, i, j, z0, halo_live, hi_, hj_);
+    epatch_load<R>(d, pa, x0, y0, z0, tc.w);
+    epatch_load<R>(d, pb, x0, y0, z0 + 1, tc.w);
+    PlaneRegs ra{}, rb{};
+    plane_load<LAYERS>(d, ra, tc, z0);
     // inputs of H^{n+1/2}(z0-1) at the own cell, needed by E(z0); on the
     // bottom face the E edges it feeds are PEC, so it is not needed there
-    const bool pro = own && z0 > 0;
+    const bool pro = z0 > 0;
     HDiff pdf{};
     float phx = 0.f, phy = 0.f, phz = 0.f;
     Psi6 pps{};
     LayerPos pL{};
     if (pro) {
-        const uint32_t c = (uint32_t)(d.off + i + sy * j + sz * (z0 - 1));
+        const uint32_t c = (uint32_t)(d.off + tc.ci) + tc.sy * tc.cj + tc.sz * (z0 - 1);
         const float ex = ldf(d.E[0], c), ey = ldf(d.E[1], c), ez = ldf(d.E[2], c);
-        pdf.ez_y = ldf(d.E[2], c + sy) - ez;
-        pdf.ey_z = ldf(d.E[1], c + sz) - ey;
-        pdf.ex_z = ldf(d.E[0], c + sz) - ex;
+        pdf.ez_y = ldf(d.E[2], c + tc.sy) - ez;
+        pdf.ey_z = ldf(d.E[1], c + tc.sz) - ey;
+        pdf.ex_z = ldf(d.E[0], c + tc.sz) - ex;
         pdf.ez_x = ldf(d.E[2], c + 1) - ez;
         pdf.ey_x = ldf(d.E[1], c + 1) - ey;
-        pdf.ex_y = ldf(d.E[0], c + sy) - ex;
+        pdf.ex_y = ldf(d.E[0], c + tc.sy) - ex;
         phx = ldf(d.H[0], c);
         phy = ldf(d.H[1], c);
         phz = ldf(d.H[2], c);
-        pL = layer_pos(d, i, j, z0 - 1);
-        load_psi_h(d, pL, pps);
+        if constexpr (LAYERS) {
+            if (tc.own) {
+                pL = layer_pos(d, i, j, z0 - 1);
+                load_psi_h(d, pL, pps);
+            }
+        }
     }
-    float sval = 0.f;
-    const bool src_col = d.src_kind != 0 && own && i >= d.src_box[0] && i <= d.src_box[1] &&
-                         j >= d.src_box[2] && j <= d.src_box[3];
-    if (src_col) sval = (float)src_value(d, level + 1);
+    tc.sval = 0.f;
+    tc.src_col = d.src_kind != 0 && tc.own && i >= d.src_box[0] && i <= d.src_box[1] &&
+                 j >= d.src_box[2] && j <= d.src_box[3];
+    if (tc.src_col) tc.sval = (float)src_value(d, level + 1);
     lds_barrier();   // caches visible
 
-    float hx_prev = 0.f, hy_prev = 0.f;
+    MarchState m;
+    m.hx_prev = 0.f;
+    m.hy_prev = 0.f;
     if (pro) {
         float oz;
-        h_apply<R>(d, sm, pL, lx, ly, 0, pdf, pps, false, phx, phy, phz, hx_prev, hy_prev, oz);
+        h_apply<R, LAYERS>(d, sm, pL, lx, ly, 0, pdf, pps, false, phx, phy, phz, m.hx_prev,
+                           m.hy_prev, oz);
     }
-    epatch_store<R>(sm, pa, 0);
-    epatch_store<R>(sm, pb, 1);
+    epatch_store<R>(sm, pa, 0, tc.w);
+    epatch_store<R>(sm, pb, 1, tc.w);
     lds_barrier();
 
-    int s0 = 0, s1 = 1, s2 = 2;   // LDS slots of planes k, k+1, k+2
-    for (int k = z0; k < z1; ++k) {
-        const int lz = k - z0 + 1;
-        // ---- requests: this plane's E and halo auxiliaries, and everything
-        //      plane k+1 needs from HBM (consumed one iteration later) ------
-        const LayerPos L = layer_pos(d, i, j, k);
-        Psi6 pe_cur{}, ph_halo{};
-        if (own) load_psi_e(d, L, pe_cur);
-        LayerPos Lh{};
-        if (halo_live) {
-            Lh = layer_pos(d, hi_, hj_, k);
-            load_psi_h(d, Lh, ph_halo);
-        }
-        EPatch<R> pe;
-        const bool more_e = k + 2 <= z1;
-        if (more_e) epatch_load<R>(d, pe, x0, y0, k + 2);
-        if (k + 1 < z1) plane_load(d, nxt_r, own, i, j, k + 1, halo_live, hi_, hj_);
-
-        const uint32_t c = (uint32_t)(d.off + i + sy * j + sz * k);
-        // ---- H^{n+1/2}(k): own cell ---------------------------------------
-        {
-            HDiff df;
-            const float ex = sm.e[s0][0][ly][lx], ey = sm.e[s0][1][ly][lx], ez = sm.e[s0][2][ly][lx];
-            df.ez_y = sm.e[s0][2][ly + 1][lx] - ez;
-            df.ey_z = sm.e[s1][1][ly][lx] - ey;
-            df.ex_z = sm.e[s1][0][ly][lx] - ex;
-            df.ez_x = sm.e[s0][2][ly][lx + 1] - ez;
-            df.ey_x = sm.e[s0][1][ly][lx + 1] - ey;
-            df.ex_y = sm.e[s0][0][ly + 1][lx] - ex;
-            float ox = 0.f, oy = 0.f, oz = 0.f;
-            if (own) {
-                h_apply<R>(d, sm, L, lx, ly, lz, df, cur_r.ph, true, cur_r.hx, cur_r.hy, cur_r.hz,
-                           ox, oy, oz);
-                stf(d.Ho[0], c, ox);
-                stf(d.Ho[1], c, oy);
-                stf(d.Ho[2], c, oz);
-            }
-            sm.h[0][ly][lx] = ox;
-            sm.h[1][ly][lx] = oy;
-            sm.h[2][ly][lx] = oz;
-        }
-        // ---- H^{n+1/2}(k): halo row y0-1 and halo column x0-1 -------------
-        if (halo_thread) {
-            float ox = 0.f, oy = 0.f, oz = 0.f;
-            if (halo_live) {
-                HDiff df;
-                const float ex = sm.e[s0][0][hly][hlx], ey = sm.e[s0][1][hly][hlx],
-                            ez = sm.e[s0][2][hly][hlx];
-                df.ez_y = sm.e[s0][2][hly + 1][hlx] - ez;
-                df.ey_z = sm.e[s1][1][hly][hlx] - ey;
-                df.ex_z = sm.e[s1][0][hly][hlx] - ex;
-                df.ez_x = sm.e[s0][2][hly][hlx + 1] - ez;
-                df.ey_x = sm.e[s0][1][hly][hlx + 1] - ey;
-                df.ex_y = sm.e[s0][0][hly + 1][hlx] - ex;
-                h_apply<R>(d, sm, Lh, hlx, hly, lz, df, ph_halo, false, cur_r.hhx, cur_r.hhy,
-                           cur_r.hhz, ox, oy, oz);
-            }
-            sm.h[0][hly][hlx] = ox;
-            sm.h[1][hly][hlx] = oy;
-            sm.h[2][hly][hlx] = oz;
-        }
-        lds_barrier();
-
-        // ---- E^{n+1}(k): own cell -----------------------------------------
-        if (own) {
-            const float hx = sm.h[0][ly][lx], hy = sm.h[1][ly][lx], hz = sm.h[2][ly][lx];
-            float dHz_y = hz - sm.h[2][ly - 1][lx];
-            float dHy_z = hy - hy_prev;
-            float dHx_z = hx - hx_prev;
-            float dHz_x = hz - sm.h[2][ly][lx - 1];
-            float dHy_x = hy - sm.h[1][ly][lx - 1];
-            float dHx_y = hx - sm.h[0][ly - 1][lx];
-            float pn;
-            if (L.inx) {
-                const float b = sm.px[PR_BE][lx], cc = sm.px[PR_CE][lx], ik = sm.px[PR_KE][lx];
-                dHz_x = lterm(dHz_x, b, cc, ik, pe_cur.v[PSI_EYX - 6], pn);
-                stf(d.psi_o[PSI_EYX], L.qx, pn);
-                dHy_x = lterm(dHy_x, b, cc, ik, pe_cur.v[PSI_EZX - 6], pn);
-                stf(d.psi_o[PSI_EZX], L.qx, pn);
-            }
-            if (L.iny) {
-                const float b = sm.py[PR_BE][ly], cc = sm.py[PR_CE][ly], ik = sm.py[PR_KE][ly];
-                dHz_y = lterm(dHz_y, b, cc, ik, pe_cur.v[PSI_EXY - 6], pn);
-                stf(d.psi_o[PSI_EXY], L.qy, pn);
-                dHx_y = lterm(dHx_y, b, cc, ik, pe_cur.v[PSI_EZY - 6], pn);
-                stf(d.psi_o[PSI_EZY], L.qy, pn);
-            }
-            if (L.inz) {
-                const float b = sm.pz[PR_BE][lz], cc = sm.pz[PR_CE][lz], ik = sm.pz[PR_KE][lz];
-                dHy_z = lterm(dHy_z, b, cc, ik, pe_cur.v[PSI_EXZ - 6], pn);
-                stf(d.psi_o[PSI_EXZ], L.qz, pn);
-                dHx_z = lterm(dHx_z, b, cc, ik, pe_cur.v[PSI_EYZ - 6], pn);
-                stf(d.psi_o[PSI_EYZ], L.qz, pn);
-            }
-            float4 cx, cy, cz;
-            if (lut_lds) {
-                cx = sm.lut[0][cur_r.idx];
-                cy = sm.lut[1][cur_r.idy];
-                cz = sm.lut[2][cur_r.idz];
-            } else {
-                cx = lut_entry(d.lut[0], cur_r.idx);
-                cy = lut_entry(d.lut[1], cur_r.idy);
-                cz = lut_entry(d.lut[2], cur_r.idz);
-            }
-            stf(d.Eo[0], c, cx.x * sm.e[s0][0][ly][lx] + cx.y * dHz_y - cx.z * dHy_z);
-            stf(d.Eo[1], c, cy.x * sm.e[s0][1][ly][lx] + cy.y * dHx_z - cy.z * dHz_x);
-            float ez = cz.x * sm.e[s0][2][ly][lx] + cz.y * dHy_x - cz.z * dHx_y;
-            if (src_col && k >= d.src_box[4] && k <= d.src_box[5]) ez += sval;
-            stf(d.Eo[2], c, ez);
-            hx_prev = hx;
-            hy_prev = hy;
-        }
-        // ---- rotate: plane k+2 into LDS, next plane's registers current ----
-        if (more_e) epatch_store<R>(sm, pe, s2);
-        cur_r = nxt_r;
-        const int sf = s0;
-        s0 = s1;
-        s1 = s2;
-        s2 = sf;
-        lds_barrier();
+    m.s0 = 0;
+    m.s1 = 1;
+    m.s2 = 2;
+    // two planes per iteration with the register sets swapping roles; an
+    // odd last plane runs after the loop
+    int k = z0;
+    for (; k + 1 < tc.z1; k += 2) {
+        march_plane<R, LAYERS>(d, sm, tc, k, ra, rb, m);
+        march_plane<R, LAYERS>(d, sm, tc, k + 1, rb, ra, m);
     }
+    if (k < tc.z1) march_plane<R, LAYERS>(d, sm, tc, k, ra, rb, m);
 }
 
 // Block b of n is dispatched to XCD b % 8; give each XCD a contiguous run
@@ -522,14 +594,58 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
 }
 
-// One launch = one leapfrog step of every instance in the table.  The first
-// `nprobe_blocks` blocks sample the probes of the input level (so sampling
-// overlaps the update instead of costing a launch of its own); the others
-// update tiles.
-template <int R>
+// Tile q of the interior box, x fastest.
+__device__ __forceinline__ void interior_tile(const TileSet &s, int q, int &tx, int &ty, int &tz)
+{
+    const int nx = s.ix1 - s.ix0, ny = s.iy1 - s.iy0;
+    tx = s.ix0 + q % nx;
+    ty = s.iy0 + (q / nx) % ny;
+    tz = s.iz0 + q / (nx * ny);
+}
+
+// Tile q of the complement of the interior box: whole xy-planes of tiles
+// outside [iz0, iz1) first, then whole x-rows outside [iy0, iy1) of the
+// planes inside, then the tiles outside [ix0, ix1) of the rows inside.
+__device__ __forceinline__ void boundary_tile(const TileSet &s, int q, int &tx, int &ty, int &tz)
+{
+    const int nix = s.ix1 - s.ix0, niy = s.iy1 - s.iy0, niz = s.iz1 - s.iz0;
+    const int plane = s.tx * s.ty;
+    const int a = (s.tz - niz) * plane;
+    if (q < a) {
+        const int z = q / plane, r = q % plane;
+        tz = z < s.iz0 ? z : z + niz;
+        ty = r / s.tx;
+        tx = r % s.tx;
+        return;
+    }
+    q -= a;
+    const int rows = (s.ty - niy) * s.tx;
+    const int b = niz * rows;
+    if (q < b) {
+        const int z = q / rows, r = q % rows;
+        const int y = r / s.tx;
+        tz = s.iz0 + z;
+        ty = y < s.iy0 ? y : y + niy;
+        tx = r % s.tx;
+        return;
+    }
+    q -= b;
+    const int cols = s.tx - nix;
+    const int z = q / (niy * cols), r = q % (niy * cols);
+    const int x = r % cols;
+    tz = s.iz0 + z;
+    ty = s.iy0 + r / cols;
+    tx = x < s.ix0 ? x : x + nix;
+}
+
+// One launch of one tile class for every instance in the table.  In the
+// boundary launch the first `nprobe_blocks` blocks sample the probes of the
+// input level (so sampling overlaps the update instead of costing a launch
+// of its own).
+template <int R, bool LAYERS>
 __global__ void __launch_bounds__(TW *R)
-k_fused(const DevGrid<float> *__restrict__ grids, const int32_t *__restrict__ block_start,
-        int ninst, int zchunk, int ntiles, int64_t level, const DevProbes *__restrict__ probes,
+k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ sets, int ninst,
+        int zchunk, int ntiles, int64_t level, const DevProbes *__restrict__ probes,
         int nprobe_blocks, int max_probes)
 {
     __shared__ Smem<R> sm;
@@ -544,46 +660,59 @@ k_fused(const DevGrid<float> *__restrict__ grids, const int32_t *__restrict__ bl
     int lo = 0, hi = ninst - 1;
     while (lo < hi) {          // last instance whose first block <= tb
         const int mid = (lo + hi + 1) >> 1;
-        if (block_start[mid] <= tb) lo = mid;
+        if ((LAYERS ? sets[mid].sb : sets[mid].si) <= tb) lo = mid;
         else hi = mid - 1;
     }
-    fused_tile<R>(grids[lo], tb - block_start[lo], zchunk, level, sm);
+    const TileSet s = sets[lo];
+    int tx, ty, tz;
+    if (LAYERS) boundary_tile(s, tb - s.sb, tx, ty, tz);
+    else interior_tile(s, tb - s.si, tx, ty, tz);
+    fused_tile<R, LAYERS>(grids[lo], tx, ty, tz, zchunk, level, sm);
 }
 
-template <int R>
-hipError_t launch_r(const DevGrid<float> *g, const int32_t *bs, int ninst, int ntiles, int zchunk,
-                    int64_t level, const DevProbes *probes, int nprobe_blocks, int max_probes,
-                    hipStream_t s)
+template <int R, bool LAYERS>
+hipError_t launch_r(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
+                    int zchunk, int64_t level, const DevProbes *probes, int nprobe_blocks,
+                    int max_probes, hipStream_t s)
 {
-    k_fused<R><<<ntiles + nprobe_blocks, TW * R, 0, s>>>(g, bs, ninst, zchunk, ntiles, level,
-                                                         probes, nprobe_blocks, max_probes);
+    k_fused<R, LAYERS><<<ntiles + nprobe_blocks, TW * R, 0, s>>>(
+        g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes);
     return hipGetLastError();
+}
+
+template <bool LAYERS>
+hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
+                        const LaunchCfg &cfg, int64_t level, const DevProbes *probes, int npb,
+                        int max_probes, hipStream_t s)
+{
+    switch (cfg.rows) {
+    case 2: return launch_r<2, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
+    case 4: return launch_r<4, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
+    case 8: return launch_r<8, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
+    case 16: return launch_r<16, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-int32_t fused_tiles(int32_t nx, int32_t ny, int32_t nz, const LaunchCfg &cfg)
-{
-    const int tx = (nx + TW - 1) / TW, ty = (ny + cfg.rows - 1) / cfg.rows;
-    const int tz = (nz + cfg.zchunk - 1) / cfg.zchunk;
-    return tx * ty * tz;
-}
-
-hipError_t launch_fused(const DevGrid<float> *grids_dev, const int32_t *block_start_dev,
-                        int32_t ninst, int32_t ntiles, const LaunchCfg &cfg, int64_t level,
+hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
+                        int32_t nb, int32_t ni, const LaunchCfg &cfg, int64_t level,
                         const DevProbes *probes_dev, int32_t max_probes, bool sample_input,
                         hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
+    if (cfg.rows != 2 && cfg.rows != 4 && cfg.rows != 8 && cfg.rows != 16)
+        return hipErrorInvalidValue;
     const int npb = (sample_input && level >= 1) ? ninst * max_probes : 0;
     if (e0) (void)hipEventRecord(e0, s);
-    hipError_t err;
-    switch (cfg.rows) {
-    case 2: err = launch_r<2>(grids_dev, block_start_dev, ninst, ntiles, cfg.zchunk, level, probes_dev, npb, max_probes, s); break;
-    case 4: err = launch_r<4>(grids_dev, block_start_dev, ninst, ntiles, cfg.zchunk, level, probes_dev, npb, max_probes, s); break;
-    case 8: err = launch_r<8>(grids_dev, block_start_dev, ninst, ntiles, cfg.zchunk, level, probes_dev, npb, max_probes, s); break;
-    case 16: err = launch_r<16>(grids_dev, block_start_dev, ninst, ntiles, cfg.zchunk, level, probes_dev, npb, max_probes, s); break;
-    default: return hipErrorInvalidValue;
-    }
+    hipError_t err = hipSuccess;
+    // the two classes write disjoint cells and read only the input level
+    if (nb + npb > 0)
+        err = launch_class<true>(grids_dev, sets_dev, ninst, nb, cfg, level, probes_dev, npb,
+                                 max_probes, s);
+    if (err == hipSuccess && ni > 0)
+        err = launch_class<false>(grids_dev, sets_dev, ninst, ni, cfg, level, probes_dev, 0,
+                                  max_probes, s);
     if (e1) (void)hipEventRecord(e1, s);
     return err;
 }

@@ -28,7 +28,8 @@ enum ProfId { PR_BE, PR_CE, PR_KE, PR_BH, PR_CH, PR_KH, PR_COUNT };
 //
 // Field storage: element (i, j, k), i in [-1, nx], j in [-1, ny],
 // k in [-1, nz], sits at  off + i + px*j + px*py*k  with py = ny + 2; the
-// guard layer stays zero.  Only i < nx, j < ny, k < nz is ever written: on
+// guard layer stays zero.  After the last plane: a zero guard of 18 rows
+// (read past by tile halos) and the 64-element sink.  Only i < nx, j < ny, k < nz is ever written: on
 // the upper faces every component is either absent or tangential-PEC zero.
 // Material ids: i + px*(j + ny*k) for the computed range.
 // Auxiliary arrays live only inside the layers:
@@ -39,12 +40,16 @@ template <typename T>
 struct DevGrid {
     T *E[3], *H[3];          // fields read this step
     T *Eo[3], *Ho[3];        // fields written this step (== E/H in place)
-    const void *ids[3];      // uint8 or uint16 per edge
+    const void *ids[3];      // uint8 or uint16 per edge; fused plans: ids[0] holds
+                             // all three as bytes 0..2 of one uint32 per cell
     const T *lut[3];         // per component [id][4] = Ca, Cb/d_first, Cb/d_second, 0
     T *psi[PSI_COUNT];       // auxiliaries read this step
     T *psi_o[PSI_COUNT];     // auxiliaries written this step (== psi in place)
     const T *prof[3];        // per axis: PR_COUNT tables of n_axis entries
     int64_t off;
+    int64_t cstride;         // bytes from component c to c+1 of E, H, Eo and Ho
+    int64_t sink;            // first of 64 elements per field array that are
+                             // written by lanes without a cell and never read
     int32_t nx, ny, nz, px, py;
     int32_t id16;
     int32_t nlut;            // entries per LUT
@@ -70,6 +75,19 @@ struct DevProbes {
 struct LaunchCfg {
     int32_t rows = 4;        // tile rows (y) per block of the fused kernel
     int32_t zchunk = 32;     // planes marched per block
+};
+
+// Tile decomposition of one grid for the fused kernels.  A tile is 64 cells
+// in x, `rows` in y and `zchunk` planes in z.  The tiles whose cells, halo
+// cells (x0-1, y0-1) and first input plane (z0-1) all lie outside every
+// absorbing layer form a box [ix0, ix1) x [iy0, iy1) x [iz0, iz1) of tile
+// indices (the condition is separable per axis); they run through the
+// interior kernel, the others through the boundary kernel.
+struct TileSet {
+    int32_t tx, ty, tz;               // tiles per axis
+    int32_t ix0, ix1, iy0, iy1, iz0, iz1;
+    int32_t nb, ni;                   // boundary / interior tiles
+    int32_t sb, si;                   // first block of this grid in each launch
 };
 
 // ---------------------------------------------------------------------------
@@ -112,6 +130,8 @@ struct Plan {
     double dt = 0, eps0 = 0, mu0 = 0, c0 = 0;
     int32_t px = 0, py = 0, pz = 0;
     size_t field_elems = 0, id_elems = 0;
+    size_t cstride = 0;                  // bytes between field components
+    size_t sink = 0;                     // first of 64 write-only elements per field array
     int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int32_t id16 = 0;
     std::vector<uint16_t> ids[3];
@@ -142,6 +162,8 @@ struct Plan {
     int64_t sampled = 0;                 // last sample written to the history ring
     int32_t parity = 0;                  // which field buffer holds the current level
     LaunchCfg cfg;
+    TileSet tiles{};                     // fused plans: decomposition on the device
+    LaunchCfg tiles_cfg{0, 0};           // the launch shape `tiles` was made for
 
     KernelTimer timer;
 
@@ -159,8 +181,8 @@ struct Batch {
     size_t ws_bytes = 0;
     char *base = nullptr;
     bool bound = false;
-    std::vector<int32_t> block_start;   // per plan: first block of its tiles
-    int32_t total_blocks = 0;
+    std::vector<TileSet> sets;          // per plan: tile decomposition and first blocks
+    int32_t nb_total = 0, ni_total = 0; // boundary / interior tiles of all plans
     int32_t max_probes = 0;
     int32_t max_nf = 0;
     KernelTimer timer;
@@ -183,18 +205,20 @@ hipError_t launch_plain_step(const DevGrid<T> &d, int64_t level, hipStream_t s,
 template <typename T>
 hipError_t launch_probe(const DevGrid<T> &d, const DevProbes &p, int64_t sample, hipStream_t s);
 hipError_t launch_dft(const DevDft &d, int64_t n_first, int64_t count, hipStream_t s);
-// One fused step of ninst grids (device table grids_dev, first tile of each
-// in block_start_dev, ntiles tiles in all).  With sample_input the launch
-// also samples every probe of the input level `level` (if level >= 1).
-hipError_t launch_fused(const DevGrid<float> *grids_dev, const int32_t *block_start_dev,
-                        int32_t ninst, int32_t ntiles, const LaunchCfg &cfg, int64_t level,
+// One fused step of ninst grids (device tables grids_dev and sets_dev;
+// nb boundary and ni interior tiles in all): a boundary launch then an
+// interior launch.  With sample_input the boundary launch also samples every
+// probe of the input level `level` (if level >= 1).
+hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
+                        int32_t nb, int32_t ni, const LaunchCfg &cfg, int64_t level,
                         const DevProbes *probes_dev, int32_t max_probes, bool sample_input,
                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
                               int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
 hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,
                             int32_t max_nf, int64_t n_first, int64_t count, hipStream_t s);
-int32_t fused_tiles(int32_t nx, int32_t ny, int32_t nz, const LaunchCfg &cfg);
+// Tile decomposition of grid P under cfg (sb, si left zero).
+TileSet make_tileset(const Plan &P, const LaunchCfg &cfg);
 
 }  // namespace fdtd
 

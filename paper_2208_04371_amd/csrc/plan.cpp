@@ -57,8 +57,8 @@ static fdtd_status guarded(Plan *p, F &&f)
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Layout of a fused plan's launch table (region r_grid).
-static constexpr size_t GRID_START_OFF = 2 * sizeof(DevGrid<float>);
-static constexpr size_t GRID_PROBES_OFF = (GRID_START_OFF + 4 + 63) & ~size_t(63);
+static constexpr size_t GRID_SET_OFF = 2 * sizeof(DevGrid<float>);
+static constexpr size_t GRID_PROBES_OFF = (GRID_SET_OFF + sizeof(TileSet) + 63) & ~size_t(63);
 
 // ---------------------------------------------------------------------------
 // finalize: everything derived from the description
@@ -258,7 +258,14 @@ static void layout(Plan &P)
     const size_t elt = P.elt;
     // static tables
     P.r_static.off = 0;
-    for (int c = 0; c < 3; ++c) take(P.r_ids[c], P.id_elems * (P.id16 ? 2 : 1));
+    if (P.g.kernel == FDTD_KERNEL_FUSED) {
+        // fused plans: the three ids of a cell packed into one 32-bit word
+        take(P.r_ids[0], P.id_elems * 4);
+        take(P.r_ids[1], 0);
+        take(P.r_ids[2], 0);
+    } else {
+        for (int c = 0; c < 3; ++c) take(P.r_ids[c], P.id_elems * (P.id16 ? 2 : 1));
+    }
     for (int c = 0; c < 3; ++c) take(P.r_lut[c], P.lut[c].size() * elt);
     for (int a = 0; a < 3; ++a) take(P.r_prof[a], P.prof[a].size() * elt);
     take(P.r_toff, std::max<size_t>(1, P.toff.size()) * 8);
@@ -278,6 +285,13 @@ static void layout(Plan &P)
     for (int b = 0; b < P.nbuf; ++b)
         for (int q = 0; q < PSI_COUNT; ++q)
             take(P.r_psi[b][q], std::max<size_t>(1, P.psi_elems[q]) * elt);
+    // the components of every field sit at one fixed stride (E and H interleave)
+    P.cstride = P.r_E[0][1].off - P.r_E[0][0].off;
+    for (int b = 0; b < P.nbuf; ++b)
+        for (int c = 1; c < 3; ++c)
+            REQUIRE(P.r_E[b][c].off - P.r_E[b][c - 1].off == P.cstride &&
+                        P.r_H[b][c].off - P.r_H[b][c - 1].off == P.cstride,
+                    FDTD_E_UNSUPPORTED, "field components are not evenly spaced");
     take(P.r_hist, std::max<size_t>(1, (size_t)P.nprobe() * 2 * P.K) * 8);
     take(P.r_acc, std::max<size_t>(1, (size_t)P.nprobe() * 2 * P.nf() * 2) * 8);
     P.r_mut.bytes = cur - P.r_mut.off;
@@ -300,8 +314,10 @@ static void finalize(Plan &P)
     P.py = g.ny + 2;
     P.pz = g.nz + 2;
     // trailing guard: tile halo rows of the fused kernel may run up to 17 rows
-    // past the last plane
-    P.field_elems = 64 + (size_t)P.px * P.py * P.pz + (size_t)P.px * 18;
+    // past the last plane; then 64 sink elements that only receive the
+    // stores of fused-kernel lanes without a cell (never read)
+    P.sink = 64 + (size_t)P.px * P.py * P.pz + (size_t)P.px * 18;
+    P.field_elems = P.sink + 64;
     P.id_elems = (size_t)P.px * g.ny * g.nz;
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) {
@@ -320,6 +336,9 @@ static void finalize(Plan &P)
     const size_t sz[PSI_COUNT] = {yl, zl, zl, xl, xl, yl, yl, zl, zl, xl, xl, yl};
     for (int q = 0; q < PSI_COUNT; ++q) P.psi_elems[q] = sz[q];
     build_coefficients(P);
+    // the fused kernel keeps the coefficient tables in LDS, indexed by 8-bit ids
+    REQUIRE(g.kernel != FDTD_KERNEL_FUSED || !P.id16, FDTD_E_UNSUPPORTED,
+            "the fused kernel supports at most 256 distinct edge coefficients");
     for (int a = 0; a < 3; ++a) build_profiles(P, a);
     build_probes(P);
     layout(P);
@@ -345,6 +364,8 @@ DevGrid<T> Plan::dev_grid() const
         d.psi_o[q] = reinterpret_cast<T *>(base + r_psi[o][q].off);
     }
     d.off = 64 + (int64_t)px * (1 + py);
+    d.cstride = (int64_t)cstride;
+    d.sink = (int64_t)sink;
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz; d.px = px; d.py = py;
     d.id16 = id16;
     d.nlut = (int32_t)(lut[0].size() / 4);
@@ -370,6 +391,40 @@ DevGrid<T> Plan::dev_grid() const
 
 template DevGrid<float> Plan::dev_grid<float>() const;
 template DevGrid<double> Plan::dev_grid<double>() const;
+
+TileSet make_tileset(const Plan &P, const LaunchCfg &cfg)
+{
+    TileSet t{};
+    const int n[3] = {P.g.nx, P.g.ny, P.g.nz};
+    const int w[3] = {64, cfg.rows, cfg.zchunk};
+    int cnt[3], b0[3], b1[3];
+    bool empty = false;
+    for (int a = 0; a < 3; ++a) {
+        cnt[a] = (n[a] + w[a] - 1) / w[a];
+        b0[a] = b1[a] = 0;
+        int first = -1, last = -1;
+        for (int q = 0; q < cnt[a]; ++q) {
+            // cells the tile touches along a: its own, the halo (or first
+            // input plane) one below
+            const int lo = std::max(q * w[a] - 1, 0), hi = std::min(q * w[a] + w[a], n[a]);
+            if (lo >= P.lo[a] && hi <= n[a] - P.hi[a]) {
+                if (first < 0) first = q;
+                last = q;
+            }
+        }
+        if (first < 0) empty = true;
+        else { b0[a] = first; b1[a] = last + 1; }
+    }
+    if (empty)
+        for (int a = 0; a < 3; ++a) b0[a] = b1[a] = 0;
+    t.tx = cnt[0]; t.ty = cnt[1]; t.tz = cnt[2];
+    t.ix0 = b0[0]; t.ix1 = b1[0];
+    t.iy0 = b0[1]; t.iy1 = b1[1];
+    t.iz0 = b0[2]; t.iz1 = b1[2];
+    t.ni = (b1[0] - b0[0]) * (b1[1] - b0[1]) * (b1[2] - b0[2]);
+    t.nb = cnt[0] * cnt[1] * cnt[2] - t.ni;
+    return t;
+}
 
 static DevProbes dev_probes(const Plan &P)
 {
@@ -426,8 +481,18 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     REQUIRE(bytes >= P.ws_bytes, FDTD_E_NOMEM, "workspace smaller than fdtd_plan_workspace_size");
     P.base = base;
     std::vector<std::vector<char>> keep;
+    if (P.g.kernel == FDTD_KERNEL_FUSED) {
+        keep.emplace_back(P.id_elems * 4);
+        uint32_t *q = reinterpret_cast<uint32_t *>(keep.back().data());
+        for (size_t t = 0; t < P.id_elems; ++t)
+            q[t] = (uint32_t)P.ids[0][t] | (uint32_t)P.ids[1][t] << 8 |
+                   (uint32_t)P.ids[2][t] << 16;
+        upload(P, P.r_ids[0], q, P.id_elems * 4, s);
+    }
     for (int c = 0; c < 3; ++c) {
-        if (P.id16) {
+        if (P.g.kernel == FDTD_KERNEL_FUSED) {
+            // packed above
+        } else if (P.id16) {
             upload(P, P.r_ids[c], P.ids[c].data(), P.id_elems * 2, s);
         } else {
             keep.emplace_back(P.id_elems);
@@ -445,7 +510,8 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     upload(P, P.r_freq, P.freqs.data(), P.freqs.size() * 8, s);
     if (P.g.kernel == FDTD_KERNEL_FUSED) {
         // launch table of the fused kernel: the descriptors of both buffer
-        // parities, the first block of the only instance (0) and the probes
+        // parities, the tile decomposition (written before each run whose
+        // launch shape differs from the uploaded one) and the probes
         DevGrid<float> g2[2];
         const int par = P.parity;
         for (int q = 0; q < 2; ++q) {
@@ -457,6 +523,9 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
         keep.emplace_back(P.r_grid.bytes, 0);
         std::memcpy(keep.back().data(), g2, sizeof g2);
         std::memcpy(keep.back().data() + GRID_PROBES_OFF, &pr, sizeof pr);
+        P.tiles = make_tileset(P, P.cfg);
+        P.tiles_cfg = P.cfg;
+        std::memcpy(keep.back().data() + GRID_SET_OFF, &P.tiles, sizeof P.tiles);
         upload(P, P.r_grid, keep.back().data(), P.r_grid.bytes, s);
     }
     hip_check(hipMemsetAsync(P.base + P.r_mut.off, 0, P.r_mut.bytes, s), "clear state");
@@ -557,6 +626,12 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
     REQUIRE(nsteps >= 0, FDTD_E_INVALID_ARG, "negative step count");
     const DevProbes pr = dev_probes(P);
     const bool fused = P.g.kernel == FDTD_KERNEL_FUSED;
+    if (fused && nsteps > 0 &&
+        (P.tiles_cfg.rows != P.cfg.rows || P.tiles_cfg.zchunk != P.cfg.zchunk)) {
+        P.tiles = make_tileset(P, P.cfg);
+        P.tiles_cfg = P.cfg;
+        upload(P, Region{P.r_grid.off + GRID_SET_OFF, sizeof(TileSet)}, &P.tiles, sizeof(TileSet), s);
+    }
     for (int64_t t = 0; t < nsteps; ++t) {
         hipEvent_t e0, e1;
         hip_check(P.timer.slot(e0, e1), "timer");
@@ -564,8 +639,8 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
             // the launch samples its input level P.step (if >= 1) as well
             const char *tab = P.base + P.r_grid.off;
             hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
-                                   reinterpret_cast<const int32_t *>(tab + GRID_START_OFF), 1,
-                                   fused_tiles(P.g.nx, P.g.ny, P.g.nz, P.cfg), P.cfg, P.step,
+                                   reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF), 1,
+                                   P.tiles.nb, P.tiles.ni, P.cfg, P.step,
                                    reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
                                    P.nprobe(), P.nprobe() > 0, s, e0, e1),
                       "fused step");
