@@ -257,7 +257,9 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
 
 /* Launch configuration of the fused kernel: tile rows per block (2, 4, 8 or
  * 16; a block is 64 x rows threads) and the number of z planes one block
- * marches through (1..64).  set returns INVALID_ARG for other values. */
+ * marches through (1..64).  set returns INVALID_ARG for other values.  The
+ * default (at creation) is 8 rows and the longest z-chunk of 32, 16, 8 or 4
+ * planes that still yields at least 2048 tiles. */
 fdtd_status fdtd_batch_get_config(const fdtd_batch *batch, int32_t *tile_rows,
                                   int32_t *zchunk);
 fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t tile_rows, int32_t zchunk);

@@ -98,6 +98,9 @@ void compute_blocks(Batch &B)
     }
     B.nb_total = nb;
     B.ni_total = ni;
+    B.lut_cap = 1;
+    for (const Plan *P : B.plans)
+        B.lut_cap = std::max<int32_t>(B.lut_cap, (int32_t)(P->lut[0].size() / 4));
 }
 
 // Upload the instance tables for the current parity of the member plans.
@@ -159,7 +162,7 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
         hipEvent_t e0, e1;
         hcheck(B.timer.slot(e0, e1), "timer");
         // every instance's step, plus sampling of its input level
-        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, P0.step, probes,
+        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, B.lut_cap, P0.step, probes,
                             B.max_probes, sample, s, e0, e1),
                "batch step");
         const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
@@ -289,6 +292,7 @@ fdtd_status fdtd_batch_create(fdtd_plan *const *plans, int32_t n, fdtd_batch **o
         for (int q = 0; q < n; ++q)
             for (int r = q + 1; r < n; ++r)
                 BREQUIRE(plans[q] != plans[r], FDTD_E_INVALID_ARG, "plan listed twice");
+        b->cfg = default_launch(b->plans.data(), b->plans.size());
         compute_blocks(*b);
     });
     if (st != FDTD_OK) {

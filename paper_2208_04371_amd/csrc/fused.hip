@@ -163,19 +163,36 @@ template <int R>
 struct Smem {
     float e[3][3][R + 2][TW + 2];   // 3 rotating E^n planes: rows y0-1..y0+R, cols x0-1..x0+64
     float h[3][R + 1][TW + 1];      // H^{n+1/2}(k): rows y0-1..y0+R-1, cols x0-1..x0+63
-    float4 lut[3][LUT_LDS];
-    float px[PR_COUNT][TW + 2];     // x profiles at x0-1 .. x0+64 (boundary tiles)
-    float py[PR_COUNT][R + 2];      // y profiles at y0-1 .. y0+R
-    float pz[PR_COUNT][ZMAX + 1];   // z profiles at z0-1 .. z0+ZMAX-1
     float dummy[TW];                // target of the writes of repeated items
 };
+
+// The block's tables in the dynamic part of LDS, sized per launch: the
+// coefficient LUTs ([3][cap] entries) and, in boundary launches, the layer
+// profiles of the tile.
+template <int R>
+struct Tabs {
+    float4 *lut;
+    float *px, *py, *pz;            // [PR_COUNT][TW+2] at x0-1.., [PR_COUNT][R+2] at y0-1..,
+    int cap;                        // [PR_COUNT][ZMAX+1] at z0-1..
+    __device__ float4 coef(int c, uint32_t id) const { return lut[c * cap + (int)id]; }
+    __device__ float prx(int tab, int p) const { return px[tab * (TW + 2) + p]; }
+    __device__ float pry(int tab, int p) const { return py[tab * (R + 2) + p]; }
+    __device__ float prz(int tab, int p) const { return pz[tab * (ZMAX + 1) + p]; }
+};
+
+template <int R>
+constexpr size_t tabs_bytes(int cap, bool layers)
+{
+    return (size_t)cap * 3 * sizeof(float4) +
+           (layers ? (size_t)PR_COUNT * (TW + 2 + R + 2 + ZMAX + 1) * sizeof(float) : 0);
+}
 
 // H^{n+1/2} from H^{n-1/2} and the six forward differences of E^n at the
 // LDS-cache positions (lx, ly, lz) of the block.  Inside the layers (LAYERS
 // kernels only) the differences take their auxiliaries; with `store` the
 // updated auxiliaries of the H components are written.
 template <int R, bool LAYERS>
-__device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Smem<R> &sm,
+__device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Tabs<R> &tb,
                                         const LayerPos &L, int lx, int ly, int lz, HDiff df,
                                         const Psi6 &ps, bool store, float hx, float hy, float hz,
                                         float &ox, float &oy, float &oz)
@@ -183,21 +200,21 @@ __device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Smem<R> &
     if constexpr (LAYERS) {
         float pn;
         if (L.inx) {
-            const float b = sm.px[PR_BH][lx], c = sm.px[PR_CH][lx], ik = sm.px[PR_KH][lx];
+            const float b = tb.prx(PR_BH, lx), c = tb.prx(PR_CH, lx), ik = tb.prx(PR_KH, lx);
             df.ez_x = lterm(df.ez_x, b, c, ik, ps.v[PSI_HYX], pn);
             if (store) stf(d.psi_o[PSI_HYX], L.qx, pn);
             df.ey_x = lterm(df.ey_x, b, c, ik, ps.v[PSI_HZX], pn);
             if (store) stf(d.psi_o[PSI_HZX], L.qx, pn);
         }
         if (L.iny) {
-            const float b = sm.py[PR_BH][ly], c = sm.py[PR_CH][ly], ik = sm.py[PR_KH][ly];
+            const float b = tb.pry(PR_BH, ly), c = tb.pry(PR_CH, ly), ik = tb.pry(PR_KH, ly);
             df.ez_y = lterm(df.ez_y, b, c, ik, ps.v[PSI_HXY], pn);
             if (store) stf(d.psi_o[PSI_HXY], L.qy, pn);
             df.ex_y = lterm(df.ex_y, b, c, ik, ps.v[PSI_HZY], pn);
             if (store) stf(d.psi_o[PSI_HZY], L.qy, pn);
         }
         if (L.inz) {
-            const float b = sm.pz[PR_BH][lz], c = sm.pz[PR_CH][lz], ik = sm.pz[PR_KH][lz];
+            const float b = tb.prz(PR_BH, lz), c = tb.prz(PR_CH, lz), ik = tb.prz(PR_KH, lz);
             df.ey_z = lterm(df.ey_z, b, c, ik, ps.v[PSI_HXZ], pn);
             if (store) stf(d.psi_o[PSI_HXZ], L.qz, pn);
             df.ex_z = lterm(df.ex_z, b, c, ik, ps.v[PSI_HYZ], pn);
@@ -331,9 +348,9 @@ struct MarchState {
 // would have to wait for the loads in flight.  Past the end of the chunk
 // the prefetches repeat the last plane (cache hits, results unused).
 template <int R, bool LAYERS>
-__device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm, const TileCtx &t,
-                                            int k, const PlaneRegs &cur, PlaneRegs &nxt,
-                                            MarchState &m)
+__device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm,
+                                            const Tabs<R> &tb, const TileCtx &t, int k,
+                                            const PlaneRegs &cur, PlaneRegs &nxt, MarchState &m)
 {
     const int lx = t.lx, ly = t.ly, hlx = t.hlx, hly = t.hly, lane = threadIdx.x & (TW - 1);
     const int s0 = m.s0, s1 = m.s1, s2 = m.s2;
@@ -369,7 +386,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
         df.ex_y = sm.e[s0][0][ly + 1][lx] - ex;
         float ox = 0.f, oy = 0.f, oz = 0.f;
         if (!LAYERS || t.own)
-            h_apply<R, LAYERS>(d, sm, L, lx, ly, lz, df, cur.ph, true, cur.hx, cur.hy, cur.hz,
+            h_apply<R, LAYERS>(d, tb, L, lx, ly, lz, df, cur.ph, true, cur.hx, cur.hy, cur.hz,
                                ox, oy, oz);
         stf(d.Ho[0], c, ox);
         stf(d.Ho[1], c, oy);
@@ -390,7 +407,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
         df.ey_x = sm.e[s0][1][hly][hlx + 1] - ey;
         df.ex_y = sm.e[s0][0][hly + 1][hlx] - ex;
         float ox, oy, oz;
-        h_apply<R, LAYERS>(d, sm, Lh, hlx, hly, lz, df, ph_halo, false, cur.hhx, cur.hhy,
+        h_apply<R, LAYERS>(d, tb, Lh, hlx, hly, lz, df, ph_halo, false, cur.hhx, cur.hhy,
                            cur.hhz, ox, oy, oz);
         // halo cells outside the grid only feed PEC edges: keep them zero
         const bool live = t.halo_live;
@@ -416,21 +433,21 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
             if (t.own) {
                 float pn;
                 if (L.inx) {
-                    const float b = sm.px[PR_BE][lx], cc = sm.px[PR_CE][lx], ik = sm.px[PR_KE][lx];
+                    const float b = tb.prx(PR_BE, lx), cc = tb.prx(PR_CE, lx), ik = tb.prx(PR_KE, lx);
                     dHz_x = lterm(dHz_x, b, cc, ik, pe_cur.v[PSI_EYX - 6], pn);
                     stf(d.psi_o[PSI_EYX], L.qx, pn);
                     dHy_x = lterm(dHy_x, b, cc, ik, pe_cur.v[PSI_EZX - 6], pn);
                     stf(d.psi_o[PSI_EZX], L.qx, pn);
                 }
                 if (L.iny) {
-                    const float b = sm.py[PR_BE][ly], cc = sm.py[PR_CE][ly], ik = sm.py[PR_KE][ly];
+                    const float b = tb.pry(PR_BE, ly), cc = tb.pry(PR_CE, ly), ik = tb.pry(PR_KE, ly);
                     dHz_y = lterm(dHz_y, b, cc, ik, pe_cur.v[PSI_EXY - 6], pn);
                     stf(d.psi_o[PSI_EXY], L.qy, pn);
                     dHx_y = lterm(dHx_y, b, cc, ik, pe_cur.v[PSI_EZY - 6], pn);
                     stf(d.psi_o[PSI_EZY], L.qy, pn);
                 }
                 if (L.inz) {
-                    const float b = sm.pz[PR_BE][lz], cc = sm.pz[PR_CE][lz], ik = sm.pz[PR_KE][lz];
+                    const float b = tb.prz(PR_BE, lz), cc = tb.prz(PR_CE, lz), ik = tb.prz(PR_KE, lz);
                     dHy_z = lterm(dHy_z, b, cc, ik, pe_cur.v[PSI_EXZ - 6], pn);
                     stf(d.psi_o[PSI_EXZ], L.qz, pn);
                     dHx_z = lterm(dHx_z, b, cc, ik, pe_cur.v[PSI_EYZ - 6], pn);
@@ -438,9 +455,9 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
                 }
             }
         }
-        const float4 cx = sm.lut[0][cur.ids & 0xffu];
-        const float4 cy = sm.lut[1][(cur.ids >> 8) & 0xffu];
-        const float4 cz = sm.lut[2][(cur.ids >> 16) & 0xffu];
+        const float4 cx = tb.coef(0, cur.ids & 0xffu);
+        const float4 cy = tb.coef(1, (cur.ids >> 8) & 0xffu);
+        const float4 cz = tb.coef(2, (cur.ids >> 16) & 0xffu);
         const float ex = cx.x * sm.e[s0][0][ly][lx] + cx.y * dHz_y - cx.z * dHy_z;
         const float ey = cy.x * sm.e[s0][1][ly][lx] + cy.y * dHx_z - cy.z * dHz_x;
         float ez = cz.x * sm.e[s0][2][ly][lx] + cz.y * dHy_x - cz.z * dHx_y;
@@ -461,7 +478,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
 
 template <int R, bool LAYERS>
 __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int zchunk,
-                           int64_t level, Smem<R> &sm)
+                           int64_t level, Smem<R> &sm, const Tabs<R> &tb)
 {
     TileCtx tc;
     tc.x0 = tx * TW;
@@ -505,20 +522,20 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     const int nlut = d.nlut;
     for (int q = t; q < 3 * nlut; q += TW * R) {
         const int c = q / nlut, e = q % nlut;
-        sm.lut[c][e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
+        tb.lut[c * tb.cap + e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
     }
     if constexpr (LAYERS) {
         for (int q = t; q < PR_COUNT * (TW + 2); q += TW * R) {
             const int tab = q / (TW + 2), p = q % (TW + 2);
-            sm.px[tab][p] = prof_at(d.prof[0], tab, d.nx, x0 - 1 + p);
+            tb.px[q] = prof_at(d.prof[0], tab, d.nx, x0 - 1 + p);
         }
         for (int q = t; q < PR_COUNT * (R + 2); q += TW * R) {
             const int tab = q / (R + 2), p = q % (R + 2);
-            sm.py[tab][p] = prof_at(d.prof[1], tab, d.ny, y0 - 1 + p);
+            tb.py[q] = prof_at(d.prof[1], tab, d.ny, y0 - 1 + p);
         }
         for (int q = t; q < PR_COUNT * (ZMAX + 1); q += TW * R) {
             const int tab = q / (ZMAX + 1), p = q % (ZMAX + 1);
-            sm.pz[tab][p] = prof_at(d.prof[2], tab, d.nz, z0 - 1 + p);
+            tb.pz[q] = prof_at(d.prof[2], tab, d.nz, z0 - 1 + p);
         }
     }
 
@@ -565,7 +582,7 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     m.hy_prev = 0.f;
     if (pro) {
         float oz;
-        h_apply<R, LAYERS>(d, sm, pL, lx, ly, 0, pdf, pps, false, phx, phy, phz, m.hx_prev,
+        h_apply<R, LAYERS>(d, tb, pL, lx, ly, 0, pdf, pps, false, phx, phy, phz, m.hx_prev,
                            m.hy_prev, oz);
     }
     epatch_store<R>(sm, pa, 0, tc.w);
@@ -579,10 +596,10 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     // odd last plane runs after the loop
     int k = z0;
     for (; k + 1 < tc.z1; k += 2) {
-        march_plane<R, LAYERS>(d, sm, tc, k, ra, rb, m);
-        march_plane<R, LAYERS>(d, sm, tc, k + 1, rb, ra, m);
+        march_plane<R, LAYERS>(d, sm, tb, tc, k, ra, rb, m);
+        march_plane<R, LAYERS>(d, sm, tb, tc, k + 1, rb, ra, m);
     }
-    if (k < tc.z1) march_plane<R, LAYERS>(d, sm, tc, k, ra, rb, m);
+    if (k < tc.z1) march_plane<R, LAYERS>(d, sm, tb, tc, k, ra, rb, m);
 }
 
 // Block b of n is dispatched to XCD b % 8; give each XCD a contiguous run
@@ -646,9 +663,16 @@ template <int R, bool LAYERS>
 __global__ void __launch_bounds__(TW *R)
 k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ sets, int ninst,
         int zchunk, int ntiles, int64_t level, const DevProbes *__restrict__ probes,
-        int nprobe_blocks, int max_probes)
+        int nprobe_blocks, int max_probes, int lut_cap)
 {
     __shared__ Smem<R> sm;
+    extern __shared__ float4 dyn_lds[];
+    Tabs<R> tb;
+    tb.cap = lut_cap;
+    tb.lut = dyn_lds;
+    tb.px = reinterpret_cast<float *>(dyn_lds + 3 * lut_cap);
+    tb.py = tb.px + PR_COUNT * (TW + 2);
+    tb.pz = tb.py + PR_COUNT * (R + 2);
     const int b = blockIdx.x;
     if (b < nprobe_blocks) {
         const int inst = b / max_probes, q = b % max_probes;
@@ -656,40 +680,40 @@ k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ se
             probe_one(grids[inst], probes[inst], q, level, reinterpret_cast<double *>(&sm));
         return;
     }
-    const int tb = xcd_tile(b - nprobe_blocks, ntiles);
+    const int tl = xcd_tile(b - nprobe_blocks, ntiles);
     int lo = 0, hi = ninst - 1;
-    while (lo < hi) {          // last instance whose first block <= tb
+    while (lo < hi) {          // last instance whose first block <= tl
         const int mid = (lo + hi + 1) >> 1;
-        if ((LAYERS ? sets[mid].sb : sets[mid].si) <= tb) lo = mid;
+        if ((LAYERS ? sets[mid].sb : sets[mid].si) <= tl) lo = mid;
         else hi = mid - 1;
     }
     const TileSet s = sets[lo];
     int tx, ty, tz;
-    if (LAYERS) boundary_tile(s, tb - s.sb, tx, ty, tz);
-    else interior_tile(s, tb - s.si, tx, ty, tz);
-    fused_tile<R, LAYERS>(grids[lo], tx, ty, tz, zchunk, level, sm);
+    if (LAYERS) boundary_tile(s, tl - s.sb, tx, ty, tz);
+    else interior_tile(s, tl - s.si, tx, ty, tz);
+    fused_tile<R, LAYERS>(grids[lo], tx, ty, tz, zchunk, level, sm, tb);
 }
 
 template <int R, bool LAYERS>
 hipError_t launch_r(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                     int zchunk, int64_t level, const DevProbes *probes, int nprobe_blocks,
-                    int max_probes, hipStream_t s)
+                    int max_probes, int lut_cap, hipStream_t s)
 {
-    k_fused<R, LAYERS><<<ntiles + nprobe_blocks, TW * R, 0, s>>>(
-        g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes);
+    k_fused<R, LAYERS><<<ntiles + nprobe_blocks, TW * R, tabs_bytes<R>(lut_cap, LAYERS), s>>>(
+        g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes, lut_cap);
     return hipGetLastError();
 }
 
 template <bool LAYERS>
 hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                         const LaunchCfg &cfg, int64_t level, const DevProbes *probes, int npb,
-                        int max_probes, hipStream_t s)
+                        int max_probes, int lut_cap, hipStream_t s)
 {
     switch (cfg.rows) {
-    case 2: return launch_r<2, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
-    case 4: return launch_r<4, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
-    case 8: return launch_r<8, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
-    case 16: return launch_r<16, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, s);
+    case 2: return launch_r<2, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 4: return launch_r<4, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 8: return launch_r<8, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 16: return launch_r<16, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -697,22 +721,23 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
 }  // namespace
 
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
-                        int32_t nb, int32_t ni, const LaunchCfg &cfg, int64_t level,
-                        const DevProbes *probes_dev, int32_t max_probes, bool sample_input,
-                        hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                        int32_t nb, int32_t ni, const LaunchCfg &cfg, int32_t lut_cap,
+                        int64_t level, const DevProbes *probes_dev, int32_t max_probes,
+                        bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (cfg.rows != 2 && cfg.rows != 4 && cfg.rows != 8 && cfg.rows != 16)
         return hipErrorInvalidValue;
+    if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
     const int npb = (sample_input && level >= 1) ? ninst * max_probes : 0;
     if (e0) (void)hipEventRecord(e0, s);
     hipError_t err = hipSuccess;
     // the two classes write disjoint cells and read only the input level
     if (nb + npb > 0)
         err = launch_class<true>(grids_dev, sets_dev, ninst, nb, cfg, level, probes_dev, npb,
-                                 max_probes, s);
+                                 max_probes, lut_cap, s);
     if (err == hipSuccess && ni > 0)
         err = launch_class<false>(grids_dev, sets_dev, ninst, ni, cfg, level, probes_dev, 0,
-                                  max_probes, s);
+                                  max_probes, lut_cap, s);
     if (e1) (void)hipEventRecord(e1, s);
     return err;
 }

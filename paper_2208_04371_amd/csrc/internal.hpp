@@ -183,6 +183,7 @@ struct Batch {
     bool bound = false;
     std::vector<TileSet> sets;          // per plan: tile decomposition and first blocks
     int32_t nb_total = 0, ni_total = 0; // boundary / interior tiles of all plans
+    int32_t lut_cap = 1;                // largest coefficient table of the plans
     int32_t max_probes = 0;
     int32_t max_nf = 0;
     KernelTimer timer;
@@ -209,16 +210,20 @@ hipError_t launch_dft(const DevDft &d, int64_t n_first, int64_t count, hipStream
 // nb boundary and ni interior tiles in all): a boundary launch then an
 // interior launch.  With sample_input the boundary launch also samples every
 // probe of the input level `level` (if level >= 1).
+// lut_cap: LUT entries per component the launch reserves in LDS (at least
+// the largest nlut of the instances, at most 256).
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
-                        int32_t nb, int32_t ni, const LaunchCfg &cfg, int64_t level,
-                        const DevProbes *probes_dev, int32_t max_probes, bool sample_input,
-                        hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                        int32_t nb, int32_t ni, const LaunchCfg &cfg, int32_t lut_cap,
+                        int64_t level, const DevProbes *probes_dev, int32_t max_probes,
+                        bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
                               int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
 hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,
                             int32_t max_nf, int64_t n_first, int64_t count, hipStream_t s);
 // Tile decomposition of grid P under cfg (sb, si left zero).
 TileSet make_tileset(const Plan &P, const LaunchCfg &cfg);
+// Default launch shape for one step of the given grids.
+LaunchCfg default_launch(const Plan *const *plans, size_t n);
 
 }  // namespace fdtd
 

@@ -392,6 +392,23 @@ DevGrid<T> Plan::dev_grid() const
 template DevGrid<float> Plan::dev_grid<float>() const;
 template DevGrid<double> Plan::dev_grid<double>() const;
 
+LaunchCfg default_launch(const Plan *const *plans, size_t n)
+{
+    // 8-row tiles, and the longest z-chunk (32, 16, 8 or 4 planes) that
+    // still gives each of the 256 CUs about 8 tiles
+    LaunchCfg c;
+    c.rows = 8;
+    for (c.zchunk = 32; c.zchunk > 4; c.zchunk /= 2) {
+        int64_t tiles = 0;
+        for (size_t q = 0; q < n; ++q) {
+            const fdtd_grid &g = plans[q]->g;
+            tiles += (int64_t)((g.nx + 63) / 64) * ((g.ny + 7) / 8) * ((g.nz + c.zchunk - 1) / c.zchunk);
+        }
+        if (tiles >= 2048) break;
+    }
+    return c;
+}
+
 TileSet make_tileset(const Plan &P, const LaunchCfg &cfg)
 {
     TileSet t{};
@@ -640,7 +657,8 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
             const char *tab = P.base + P.r_grid.off;
             hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
                                    reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF), 1,
-                                   P.tiles.nb, P.tiles.ni, P.cfg, P.step,
+                                   P.tiles.nb, P.tiles.ni, P.cfg,
+                                   std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)), P.step,
                                    reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
                                    P.nprobe(), P.nprobe() > 0, s, e0, e1),
                       "fused step");
@@ -717,6 +735,8 @@ fdtd_status fdtd_plan_create(const fdtd_grid *grid, fdtd_plan **out)
     p->g = g;
     p->bnd.m = 3.0;
     p->bnd.kappa_max = 1.0;
+    const Plan *one = p;
+    p->cfg = default_launch(&one, 1);
     *out = p;
     return FDTD_OK;
 }

@@ -253,3 +253,52 @@ def test_full_size_microstrip_window(fd):
     Vg, Ig = sim.spectra()
     Vo, Io = o.spectra()
     assert _rel(Vg, Vo) < 1e-4 and _rel(Ig, Io) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# the 1024x512x256 line and the 16-instance sweep at full size, in their
+# default launch shapes
+# ---------------------------------------------------------------------------
+
+def test_full_size_line_light_cone(fd):
+    """The full 1024x512x256 layered lossy line for 100 steps.  The oracle
+    runs a window around the source whose cut faces lie 102 cells beyond the
+    checked box: inside the light cone the two must agree (the window
+    property itself is checked on the CPU)."""
+    n = 100
+    p = W.large_line(nsteps=n)
+    _say(f"full-size line {p.nx}x{p.ny}x{p.nz}, {n} steps, light-cone window")
+    sim = fd.Simulation(p, fused=True).run()
+    box = (0, 140, 140, 372, 0, 200)
+    o = oracle.Oracle(W.window(p, box)).run(n)
+    m = n + 2
+    full_sl = (slice(0, box[5] - m), slice(box[2] + m, box[3] - m), slice(0, box[1] - m))
+    win_sl = (slice(0, box[5] - m), slice(m, box[3] - box[2] - m), slice(0, box[1] - m))
+    got = [sim.field(c)[full_sl].copy() for c in range(6)]
+    sim.close()
+    ref = [o.field(c)[win_sl] for c in range(6)]
+    assert max(np.max(np.abs(r)) for r in ref[:3]) > 0
+    errs = _field_errors(got, ref, "l2")
+    _say("  field errors (l2): " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) < 1e-4
+
+
+def test_geometry_sweep_batch_matches_oracle(fd):
+    """The 16 uneven sweep instances as one batch for 120 steps; the
+    smallest and the largest instance checked whole against the oracle."""
+    n = 120
+    probs = W.geometry_sweep(nsteps=n)
+    _say(f"sweep batch of {len(probs)}, {n} steps")
+    bs = fd.BatchSimulation(probs)
+    bs.run(n)
+    for q in (0, len(probs) - 1):
+        p = probs[q]
+        o = oracle.Oracle(p).run(n)
+        errs = _field_errors([bs.field(q, c) for c in range(6)], _fields(o), "l2")
+        _say(f"  instance {q} {p.nx}x{p.ny}x{p.nz} field errors (l2): " +
+             " ".join(f"{e:.1e}" for e in errs))
+        assert max(errs) < 1e-4
+        Vb, Ib = bs.spectra(q)
+        Vo, Io = o.spectra()
+        assert _rel(Vb, Vo) < 1e-4 and _rel(Ib, Io) < 1e-4
+    bs.close()

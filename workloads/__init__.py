@@ -365,6 +365,43 @@ def step_circuit(nx=400, ny=120, nz=80, delta=5e-9, w1=8, w2=16, step_x=200, sub
             "inc2": prob("inc2", "uniform2", src2), "tot2": prob("tot2", "step", src2)}
 
 
+def window(p: Problem, box: Tuple[int, int, int, int, int, int], name: str = "") -> Problem:
+    """The cells [x0, x1) x [y0, y1) x [z0, z1) of ``p`` as a problem of
+    their own, for light-cone checks: faces that are faces of ``p`` keep their
+    boundary and layers, cut faces become PEC.  The source is clipped to the
+    window (its nodes re-indexed); ports and point probes are dropped.  After
+    n steps the fields of the window agree with those of ``p`` on every cell
+    more than n + 1 cells away from a cut face."""
+    x0, x1, y0, y1, z0, z1 = box
+    lo, hi = (x0, y0, z0), (x1, y1, z1)
+    n = (p.nx, p.ny, p.nz)
+    assert all(0 <= lo[a] < hi[a] <= n[a] for a in range(3))
+    faces, pml = [], []
+    for a in range(3):
+        for side, cut in ((0, lo[a] > 0), (1, hi[a] < n[a])):
+            faces.append(PEC if cut else p.faces[2 * a + side])
+            pml.append(0 if cut else p.pml_cells[2 * a + side])
+    src = None
+    if p.source is not None:
+        s = p.source
+        b = list(s.box)
+        clipped = []
+        for a in range(3):
+            c0, c1 = max(b[2 * a], lo[a]), min(b[2 * a + 1], hi[a] - 1)
+            clipped += [c0 - lo[a], c1 - lo[a]]
+        if all(clipped[2 * a] <= clipped[2 * a + 1] for a in range(3)):
+            src = Source(s.kind, tuple(clipped), s.t0, s.width, s.fc, s.bandwidth, s.amplitude,
+                         s.comp)
+    return Problem(
+        name=name or f"{p.name}_window", nx=x1 - x0, ny=y1 - y0, nz=z1 - z0, dx=p.dx, dy=p.dy,
+        dz=p.dz, courant=p.courant, normalized=p.normalized,
+        materials=[Material(m.eps_r, m.sigma, m.pec) for m in p.materials],
+        cells=np.ascontiguousarray(p.cells[z0:z1, y0:y1, x0:x1]), faces=tuple(faces),
+        pml_cells=tuple(pml), pml_m=p.pml_m, pml_sigma_max=p.pml_sigma_max,
+        pml_kappa_max=p.pml_kappa_max, pml_alpha_max=p.pml_alpha_max, source=src,
+        freqs=p.freqs.copy(), nsteps=p.nsteps, fp32=p.fp32)
+
+
 # ---------------------------------------------------------------------------
 # Test-only geometries
 # ---------------------------------------------------------------------------
