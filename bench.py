@@ -19,7 +19,6 @@ Prints one JSON line (see the fields below).  Also measured and reported:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -52,18 +51,11 @@ def algorithmic_bytes(p, field_bytes=4, id_bytes=1, fused=True):
     return cells * (vals * field_bytes + 3 * id_bytes) + layer * 8 * field_bytes, cells, layer
 
 
-def source_hash():
-    h = hashlib.sha256()
-    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_2208_04371_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2208_04371_amd", "csrc", fn), "rb") as f:
-            h.update(fn.encode() + f.read())
-    return h.hexdigest()[:16]
-
-
-def load_traffic(kernel_tag, workload):
-    """HBM traffic per launch from a committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources."""
-    path = os.path.join(PROFILE_DIR, f"{kernel_tag}_{workload}_traffic.json")
+def load_traffic(workload):
+    """HBM-side bytes per fused step from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    from paper_2208_04371_amd.profiling import source_hash
+    path = os.path.join(PROFILE_DIR, f"fused_step_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -89,18 +81,19 @@ def golden_accuracy(freqs, r):
     return out
 
 
-def stream_copy(nbytes=1 << 30, reps=5):
-    """Device-to-device copy of a known size: the practical bandwidth ceiling
-    of the box and the calibration kernel for the counter-based traffic."""
+def stream_copy(fd, nbytes=1 << 30, reps=5):
+    """The library's streaming copy of a known size (on torch's current
+    stream): the practical bandwidth ceiling of the GPU and the calibration
+    kernel of the counter-based traffic."""
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
+    fd.fdtd_device_copy(b, a)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        fd.fdtd_device_copy(b, a)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -186,7 +179,7 @@ def main():
 
     torch.cuda.set_device(0)
     prob = W.single_microstrip(twin=False)
-    copy_gbs = stream_copy()
+    copy_gbs = stream_copy(fd)
 
     sim = fd.Simulation(prob, fused=True)
     for _ in range(args.warmup):
@@ -208,7 +201,7 @@ def main():
     bytes_launch, cells, layer_cells = algorithmic_bytes(prob)
     kavg_s = kms / max(launches, 1) * 1e-3
     achieved = bytes_launch / kavg_s / 1e9
-    traffic = load_traffic("fused_step", "microstrip_400x120x80")
+    traffic = load_traffic("microstrip_400x120x80")
 
     line = {
         "metric": METRIC,
@@ -235,7 +228,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_fused (one launch per leapfrog step)",
+            "kernel": "k_fused<R, layers>: one leapfrog step = boundary-tile launch + "
+                      "interior-tile launch, timed together",
             "bytes_per_launch": bytes_launch,
             "avg_launch_us": round(kavg_s * 1e6, 3),
             "launches": launches,
@@ -277,6 +271,18 @@ def main():
             "avg_step_us": round(bms / max(bl, 1) * 1e3, 2),
             "hbm_frac": round(bytes_b / (bms / max(bl, 1) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bs.close()
+        # the 1024x512x256 layered lossy line: the grid far larger than the
+        # caches, in its default launch shape
+        lp = W.large_line(nsteps=300)
+        dt, kavg_ms = measure_variant(fd, lp, True, fd.FP32, 300)
+        lb, lcells, llayer = algorithmic_bytes(lp)
+        var["line_1024x512x256_fused"] = {
+            "value": round(lp.ncells * 300 / dt / 1e6, 1), "unit": "Mcell-updates/s",
+            "timesteps": 300, "cells": lcells, "layer_cells": llayer,
+            "avg_step_us": round(kavg_ms * 1e3, 2), "bytes_per_step": lb,
+            "achieved_GBs": round(lb / (kavg_ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(lb / (kavg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic("line_1024x512x256")}
         line["variants"] = var
 
     if not args.no_cpu_baseline:

@@ -315,6 +315,17 @@ fdtd_status fdtd_sparams(int32_t np, int32_t nf, const double *f, const double *
                          const double *Iinc, const double *Vtot, double z_ref,
                          double *S_star, double *S, double *Zr, double *Z0, double *tau);
 
+/* ---- measurement support ------------------------------------------------ */
+
+/* Copy `bytes` from src to dst, both device memory, on `stream`
+ * (asynchronous).  A plain streaming copy: every byte read once and written
+ * once, so its rate is the practical memory-bandwidth ceiling of the GPU
+ * and its memory counters calibrate those of the field update.  Both
+ * pointers and `bytes` must be multiples of 16 and the ranges must not
+ * overlap (INVALID_ARG otherwise); HIP if the launch fails.  Not part of
+ * the method. */
+fdtd_status fdtd_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Text for a status code. */
 const char *fdtd_status_string(fdtd_status s);
 

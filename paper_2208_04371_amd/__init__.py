@@ -206,6 +206,16 @@ def fdtd_sparams(freqs, Vinc, Iinc, Vtot, z_ref=50.0):
     return {"S_star": c(Ss), "S": c(S), "Zr": c(Zr), "Z0": c(Z0) if n == 2 else None, "tau": tau}
 
 
+def fdtd_device_copy(dst, src, stream=None):
+    """Copy the device tensor ``src`` into ``dst`` (same byte size, 16-byte
+    multiples, no overlap) with the library's streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("fdtd_device_copy: size mismatch")
+    check(lib().fdtd_device_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                                 _stream(stream)), "fdtd_device_copy")
+
+
 def protocol_from_runs(spectra):
     """Arrange the spectra of the four runs of a 2-port's protocol ("inc1",
     "inc2": port j driven on its uniform line; "tot1", "tot2": the full

@@ -100,6 +100,7 @@ SIGNATURES = {
     "fdtd_batch_get_kernel_time": (I32, [P, PD, C.POINTER(I64)]),
     "fdtd_sparams": (I32, [I32, I32, PD, PD, PD, PD, C.c_double, PD, PD, PD, PD, PD]),
     "fdtd_status_string": (C.c_char_p, [I32]),
+    "fdtd_device_copy": (I32, [P, P, C.c_size_t, P]),
 }
 
 _lib = None

@@ -179,3 +179,13 @@ def test_sparams_rejects_bad_input(fd):
     with pytest.raises(fd.FdtdError) as e:
         fd.fdtd_sparams(np.zeros(0), np.zeros((1, 0)), np.zeros((1, 0)), np.zeros((1, 1, 0)))
     assert e.value.code == -1
+
+
+def test_device_copy_validates_arguments(fd):
+    """Argument checks of the streaming copy happen before any HIP call."""
+    L = fd.lib()
+    assert L.fdtd_device_copy(None, None, 0, None) == 0           # nothing to copy
+    assert L.fdtd_device_copy(None, C.c_void_p(4096), 64, None) == -1
+    assert L.fdtd_device_copy(C.c_void_p(4096), C.c_void_p(8192 + 8), 64, None) == -1
+    assert L.fdtd_device_copy(C.c_void_p(4096), C.c_void_p(8192), 60, None) == -1
+    assert L.fdtd_device_copy(C.c_void_p(4096), C.c_void_p(4096 + 32), 64, None) == -1
