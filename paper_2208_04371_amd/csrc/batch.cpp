@@ -156,7 +156,6 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
     const TileSet *sets = reinterpret_cast<const TileSet *>(tb + t.sets);
     const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes);
     Plan &P0 = *B.plans[0];
-    if (nsteps > 0) hcheck(B.side.ensure(), "side stream");
     const bool sample = B.max_probes > 0;
     for (int64_t q = 0; q < nsteps; ++q) {
         const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
@@ -164,7 +163,7 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
         hcheck(B.timer.slot(e0, e1), "timer");
         // every instance's step, plus sampling of its input level
         hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, B.lut_cap, P0.step, probes,
-                            B.max_probes, sample, s, &B.side, e0, e1),
+                            B.max_probes, sample, s, e0, e1),
                "batch step");
         const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
         for (Plan *P : B.plans) {
@@ -463,7 +462,6 @@ void fdtd_batch_destroy(fdtd_batch *batch)
         P->bound = false;
     }
     batch->timer.destroy();
-    batch->side.destroy();
     delete batch;
 }
 

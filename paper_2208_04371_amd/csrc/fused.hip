@@ -720,54 +720,25 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
 
 }  // namespace
 
-hipError_t SideStream::ensure()
-{
-    if (s) return hipSuccess;
-    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
-    if (e != hipSuccess) destroy();
-    return e;
-}
-
-void SideStream::destroy()
-{
-    if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
-    if (s) (void)hipStreamDestroy(s);
-    s = nullptr;
-    fork = join = nullptr;
-}
-
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
                         int32_t nb, int32_t ni, const LaunchCfg &cfg, int32_t lut_cap,
                         int64_t level, const DevProbes *probes_dev, int32_t max_probes,
-                        bool sample_input, hipStream_t s, const SideStream *side,
-                        hipEvent_t e0, hipEvent_t e1)
+                        bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (cfg.rows != 2 && cfg.rows != 4 && cfg.rows != 8 && cfg.rows != 16)
         return hipErrorInvalidValue;
     if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
     const int npb = (sample_input && level >= 1) ? ninst * max_probes : 0;
+    if (e0) (void)hipEventRecord(e0, s);
     hipError_t err = hipSuccess;
-    if (e0) err = hipEventRecord(e0, s);
     // the two classes write disjoint cells and read only the input level
-    const bool fork = nb + npb > 0 && ni > 0 && side && side->s;
-    if (err == hipSuccess && fork) {
-        err = hipEventRecord(side->fork, s);
-        if (err == hipSuccess) err = hipStreamWaitEvent(side->s, side->fork, 0);
-    }
-    if (err == hipSuccess && nb + npb > 0)
+    if (nb + npb > 0)
         err = launch_class<true>(grids_dev, sets_dev, ninst, nb, cfg, level, probes_dev, npb,
                                  max_probes, lut_cap, s);
     if (err == hipSuccess && ni > 0)
         err = launch_class<false>(grids_dev, sets_dev, ninst, ni, cfg, level, probes_dev, 0,
-                                  max_probes, lut_cap, fork ? side->s : s);
-    if (err == hipSuccess && fork) {
-        err = hipEventRecord(side->join, side->s);
-        if (err == hipSuccess) err = hipStreamWaitEvent(s, side->join, 0);
-    }
-    if (err == hipSuccess && e1) err = hipEventRecord(e1, s);
+                                  max_probes, lut_cap, s);
+    if (e1) (void)hipEventRecord(e1, s);
     return err;
 }
 

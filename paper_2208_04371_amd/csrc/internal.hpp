@@ -114,15 +114,6 @@ struct KernelTimer {
     void destroy();
 };
 
-// A second stream (default priority) with the two events that fork work
-// from the run stream onto it and join it back; created on first use.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    hipError_t ensure();
-    void destroy();
-};
-
 struct Plan {
     fdtd_grid g{};
     std::vector<uint8_t> cells;
@@ -175,7 +166,6 @@ struct Plan {
     LaunchCfg tiles_cfg{0, 0};           // the launch shape `tiles` was made for
 
     KernelTimer timer;
-    SideStream side;                     // fused plans: the interior-tile launch
 
     std::string err;
 
@@ -197,7 +187,6 @@ struct Batch {
     int32_t max_probes = 0;
     int32_t max_nf = 0;
     KernelTimer timer;
-    SideStream side;                    // the interior-tile launch
     std::string err;
 };
 
@@ -222,15 +211,11 @@ hipError_t launch_dft(const DevDft &d, int64_t n_first, int64_t count, hipStream
 // interior launch.  With sample_input the boundary launch also samples every
 // probe of the input level `level` (if level >= 1).
 // lut_cap: LUT entries per component the launch reserves in LDS (at least
-// the largest nlut of the instances, at most 256).  With `side` the interior
-// launch runs on the side stream, forked from and joined back into s, so the
-// two classes overlap (they write disjoint cells and read only the input
-// level); e0/e1 (if set) bracket the whole step on s.
+// the largest nlut of the instances, at most 256).
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
                         int32_t nb, int32_t ni, const LaunchCfg &cfg, int32_t lut_cap,
                         int64_t level, const DevProbes *probes_dev, int32_t max_probes,
-                        bool sample_input, hipStream_t s, const SideStream *side,
-                        hipEvent_t e0, hipEvent_t e1);
+                        bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
                               int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
 hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,

@@ -643,7 +643,6 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
     REQUIRE(nsteps >= 0, FDTD_E_INVALID_ARG, "negative step count");
     const DevProbes pr = dev_probes(P);
     const bool fused = P.g.kernel == FDTD_KERNEL_FUSED;
-    if (fused && nsteps > 0) hip_check(P.side.ensure(), "side stream");
     if (fused && nsteps > 0 &&
         (P.tiles_cfg.rows != P.cfg.rows || P.tiles_cfg.zchunk != P.cfg.zchunk)) {
         P.tiles = make_tileset(P, P.cfg);
@@ -661,7 +660,7 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
                                    P.tiles.nb, P.tiles.ni, P.cfg,
                                    std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)), P.step,
                                    reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
-                                   P.nprobe(), P.nprobe() > 0, s, &P.side, e0, e1),
+                                   P.nprobe(), P.nprobe() > 0, s, e0, e1),
                       "fused step");
             P.parity = 1 - P.parity;
             if (P.nprobe() > 0 && P.step >= 1) P.sampled = std::max(P.sampled, P.step);
@@ -746,7 +745,6 @@ void fdtd_plan_destroy(fdtd_plan *plan)
 {
     if (!plan) return;
     plan->timer.destroy();
-    plan->side.destroy();
     delete plan;
 }
 
