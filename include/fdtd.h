@@ -245,7 +245,7 @@ fdtd_status fdtd_batch_reset(fdtd_batch *batch, void *stream);
 /* Advance every member plan by nsteps steps in lockstep.  Asynchronous. */
 fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 
-/* Choose the tile height (2, 4, 8, 16 rows) and z-chunk (4, 8, 16, 32, 64
+/* Choose the tile height (2, 4, 8, 12, 16 rows) and z-chunk (4, 8, 16, 32, 64
  * planes) of the batched kernel by timing each candidate
  * for `trial_steps` steps; the member states are reset afterwards.
  * cache_path (may be NULL) names a JSON file keyed by GPU architecture and
@@ -255,8 +255,8 @@ fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,
                                 void *stream, int32_t *best_index);
 
-/* Launch configuration of the fused kernel: tile rows per block (2, 4, 8 or
- * 16; a block is 64 x rows threads) and the number of z planes one block
+/* Launch configuration of the fused kernel: tile rows per block (2, 4, 8,
+ * 12 or 16; a block is 64 x rows threads) and the number of z planes one block
  * marches through (1..64).  set returns INVALID_ARG for other values.  The
  * default (at creation) is 8 rows and the longest z-chunk of 32, 16, 8 or 4
  * planes that still yields at least 2048 tiles. */

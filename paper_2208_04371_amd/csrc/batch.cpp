@@ -183,7 +183,7 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
 
 // ---- autotuner -------------------------------------------------------------
 // Candidates: tile rows x z-chunk (1 << 20 = a whole column per block).
-const int TUNE_ROWS[] = {2, 4, 8, 16};
+const int TUNE_ROWS[] = {2, 4, 8, 12, 16};
 const int TUNE_Z[] = {4, 8, 16, 32, 64};
 
 // Key: the shapes of the member grids, in order.
@@ -236,7 +236,7 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &z)
         if (e.first != key) continue;
         double ms = 0;
         if (std::sscanf(e.second.c_str(), "%d , %d , %lf", &rows, &z, &ms) >= 2) {
-            const bool ok_rows = rows == 2 || rows == 4 || rows == 8 || rows == 16;
+            const bool ok_rows = valid_rows(rows);
             return ok_rows && z >= 1 && z <= 64;
         }
     }
@@ -368,8 +368,7 @@ fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t rows, int32_t zchun
 {
     if (!batch) return FDTD_E_INVALID_ARG;
     return bguard(batch, [&]() {
-        BREQUIRE(rows == 2 || rows == 4 || rows == 8 || rows == 16,
-                 FDTD_E_INVALID_ARG, "tile rows must be 2, 4, 8 or 16");
+        BREQUIRE(valid_rows(rows), FDTD_E_INVALID_ARG, "tile rows must be 2, 4, 8, 12 or 16");
         BREQUIRE(zchunk >= 1 && zchunk <= 64, FDTD_E_INVALID_ARG, "z-chunk must be in [1, 64]");
         batch->cfg.rows = rows;
         batch->cfg.zchunk = zchunk;

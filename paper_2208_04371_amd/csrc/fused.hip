@@ -120,9 +120,9 @@ __device__ __forceinline__ LayerPos layer_pos(const DevGrid<float> &d, int i, in
     L.inx = layer_slot(i, d.lo[0], d.hi[0], d.nx, s);
     L.qx = L.inx ? (uint32_t)(s + (d.lo[0] + d.hi[0]) * (j + d.ny * k)) : 0u;
     L.iny = layer_slot(j, d.lo[1], d.hi[1], d.ny, s);
-    L.qy = L.iny ? (uint32_t)(i + d.px * (s + (d.lo[1] + d.hi[1]) * k)) : 0u;
+    L.qy = L.iny ? (uint32_t)(i + d.nx * (s + (d.lo[1] + d.hi[1]) * k)) : 0u;
     L.inz = layer_slot(k, d.lo[2], d.hi[2], d.nz, s);
-    L.qz = L.inz ? (uint32_t)(i + d.px * (j + d.ny * s)) : 0u;
+    L.qz = L.inz ? (uint32_t)(i + d.nx * (j + d.ny * s)) : 0u;
     return L;
 }
 
@@ -319,7 +319,7 @@ __device__ __forceinline__ void plane_load(const DevGrid<float> &d, PlaneRegs &r
     r.hy = ldf(d.H[1], c);
     r.hz = ldf(d.H[2], c);
     r.ids = gld(static_cast<const uint32_t *>(d.ids[0]),
-                (uint32_t)(t.ci + d.px * (t.cj + d.ny * k)));
+                (uint32_t)(t.ci + d.nx * (t.cj + d.ny * k)));
     const uint32_t h = (uint32_t)(d.off + t.chi) + t.sy * t.chj + t.sz * k;
     r.hhx = ldf(d.H[0], h);
     r.hhy = ldf(d.H[1], h);
@@ -713,6 +713,7 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
     case 2: return launch_r<2, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
     case 4: return launch_r<4, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
     case 8: return launch_r<8, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 12: return launch_r<12, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
     case 16: return launch_r<16, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
     default: return hipErrorInvalidValue;
     }
@@ -725,8 +726,7 @@ hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev
                         int64_t level, const DevProbes *probes_dev, int32_t max_probes,
                         bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (cfg.rows != 2 && cfg.rows != 4 && cfg.rows != 8 && cfg.rows != 16)
-        return hipErrorInvalidValue;
+    if (!valid_rows(cfg.rows)) return hipErrorInvalidValue;
     if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
     const int npb = (sample_input && level >= 1) ? ninst * max_probes : 0;
     if (e0) (void)hipEventRecord(e0, s);

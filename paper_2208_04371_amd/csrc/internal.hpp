@@ -31,11 +31,13 @@ enum ProfId { PR_BE, PR_CE, PR_KE, PR_BH, PR_CH, PR_KH, PR_COUNT };
 // guard layer stays zero.  After the last plane: a zero guard of 18 rows
 // (read past by tile halos) and the 64-element sink.  Only i < nx, j < ny, k < nz is ever written: on
 // the upper faces every component is either absent or tangential-PEC zero.
-// Material ids: i + px*(j + ny*k) for the computed range.
+// Material ids: i + nx*(j + ny*k).
 // Auxiliary arrays live only inside the layers:
 //   x-layers  xs + Lx*(j + ny*k)   xs = i (i < lo) or i - nx + Lx
-//   y-layers  i + px*(ys + Ly*k)
-//   z-layers  i + px*(j + ny*zs)
+//   y-layers  i + nx*(ys + Ly*k)
+//   z-layers  i + nx*(j + ny*zs)
+// Fused plans ping-pong the H auxiliaries; E auxiliaries (read and written
+// only by the thread that owns the cell) are updated in place.
 template <typename T>
 struct DevGrid {
     T *E[3], *H[3];          // fields read this step
@@ -76,6 +78,12 @@ struct LaunchCfg {
     int32_t rows = 4;        // tile rows (y) per block of the fused kernel
     int32_t zchunk = 32;     // planes marched per block
 };
+
+// Tile heights the fused kernel is instantiated for.
+inline bool valid_rows(int32_t rows)
+{
+    return rows == 2 || rows == 4 || rows == 8 || rows == 12 || rows == 16;
+}
 
 // Tile decomposition of one grid for the fused kernels.  A tile is 64 cells
 // in x, `rows` in y and `zchunk` planes in z.  The tiles whose cells, halo

@@ -92,12 +92,12 @@ __global__ void __launch_bounds__(BX *BY) k_h_plain(DevGrid<T> d)
         dEy_x = layer_term(dEy_x, d.prof[0], d.nx, i, 0, true, d.psi[PSI_HZX], q);
     }
     if (in_layer(j, d.lo[1], d.hi[1], d.ny, ys)) {
-        const int64_t q = i + (int64_t)d.px * (ys + (int64_t)Ly * k);
+        const int64_t q = i + (int64_t)d.nx * (ys + (int64_t)Ly * k);
         dEz_y = layer_term(dEz_y, d.prof[1], d.ny, j, 0, true, d.psi[PSI_HXY], q);
         dEx_y = layer_term(dEx_y, d.prof[1], d.ny, j, 0, true, d.psi[PSI_HZY], q);
     }
     if (in_layer(k, d.lo[2], d.hi[2], d.nz, zs)) {
-        const int64_t q = i + (int64_t)d.px * (j + (int64_t)d.ny * zs);
+        const int64_t q = i + (int64_t)d.nx * (j + (int64_t)d.ny * zs);
         dEy_z = layer_term(dEy_z, d.prof[2], d.nz, k, 0, true, d.psi[PSI_HXZ], q);
         dEx_z = layer_term(dEx_z, d.prof[2], d.nz, k, 0, true, d.psi[PSI_HYZ], q);
     }
@@ -130,16 +130,16 @@ __global__ void __launch_bounds__(BX *BY) k_e_plain(DevGrid<T> d, int64_t level)
         dHy_x = layer_term(dHy_x, d.prof[0], d.nx, i, 0, false, d.psi[PSI_EZX], q);
     }
     if (in_layer(j, d.lo[1], d.hi[1], d.ny, ys)) {
-        const int64_t q = i + (int64_t)d.px * (ys + (int64_t)Ly * k);
+        const int64_t q = i + (int64_t)d.nx * (ys + (int64_t)Ly * k);
         dHz_y = layer_term(dHz_y, d.prof[1], d.ny, j, 0, false, d.psi[PSI_EXY], q);
         dHx_y = layer_term(dHx_y, d.prof[1], d.ny, j, 0, false, d.psi[PSI_EZY], q);
     }
     if (in_layer(k, d.lo[2], d.hi[2], d.nz, zs)) {
-        const int64_t q = i + (int64_t)d.px * (j + (int64_t)d.ny * zs);
+        const int64_t q = i + (int64_t)d.nx * (j + (int64_t)d.ny * zs);
         dHy_z = layer_term(dHy_z, d.prof[2], d.nz, k, 0, false, d.psi[PSI_EXZ], q);
         dHx_z = layer_term(dHx_z, d.prof[2], d.nz, k, 0, false, d.psi[PSI_EYZ], q);
     }
-    const int64_t qi = i + (int64_t)d.px * (j + (int64_t)d.ny * k);
+    const int64_t qi = i + (int64_t)d.nx * (j + (int64_t)d.ny * k);
     const T *cx = d.lut[0] + 4 * edge_id(d, 0, qi);
     const T *cy = d.lut[1] + 4 * edge_id(d, 1, qi);
     const T *cz = d.lut[2] + 4 * edge_id(d, 2, qi);

@@ -141,7 +141,7 @@ static void build_coefficients(Plan &P)
                         last_key = key;
                         last_id = id;
                     }
-                    P.ids[comp][(size_t)i + (size_t)P.px * ((size_t)j + (size_t)ny * k)] =
+                    P.ids[comp][(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] =
                         (uint16_t)std::min(id, 65535);
                 }
             }
@@ -282,9 +282,14 @@ static void layout(Plan &P)
             take(P.r_E[b][c], P.field_elems * elt);
             take(P.r_H[b][c], P.field_elems * elt);
         }
+    // ping-pong only for the H auxiliaries: tile halos read those of
+    // neighbouring cells, while an E auxiliary is read and written by the
+    // thread that owns its cell alone, so it is updated in place
     for (int b = 0; b < P.nbuf; ++b)
-        for (int q = 0; q < PSI_COUNT; ++q)
-            take(P.r_psi[b][q], std::max<size_t>(1, P.psi_elems[q]) * elt);
+        for (int q = 0; q < PSI_COUNT; ++q) {
+            if (b > 0 && q >= PSI_EXY) P.r_psi[b][q] = P.r_psi[0][q];
+            else take(P.r_psi[b][q], std::max<size_t>(1, P.psi_elems[q]) * elt);
+        }
     // the components of every field sit at one fixed stride (E and H interleave)
     P.cstride = P.r_E[0][1].off - P.r_E[0][0].off;
     for (int b = 0; b < P.nbuf; ++b)
@@ -310,7 +315,8 @@ static void finalize(Plan &P)
     P.eps0 = 1.0 / (P.mu0 * P.c0 * P.c0);
     const double s = 1.0 / (g.dx * g.dx) + 1.0 / (g.dy * g.dy) + 1.0 / (g.dz * g.dz);
     P.dt = g.courant / (P.c0 * std::sqrt(s));
-    P.px = (int32_t)(((size_t)g.nx + 2 + 63) / 64 * 64);
+    // x rows padded to 32 elements: 64-lane row loads stay on whole 128-byte lines
+    P.px = (int32_t)(((size_t)g.nx + 2 + 31) / 32 * 32);
     P.py = g.ny + 2;
     P.pz = g.nz + 2;
     // trailing guard: tile halo rows of the fused kernel may run up to 17 rows
@@ -318,7 +324,7 @@ static void finalize(Plan &P)
     // stores of fused-kernel lanes without a cell (never read)
     P.sink = 64 + (size_t)P.px * P.py * P.pz + (size_t)P.px * 18;
     P.field_elems = P.sink + 64;
-    P.id_elems = (size_t)P.px * g.ny * g.nz;
+    P.id_elems = (size_t)g.nx * g.ny * g.nz;
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) {
         P.lo[a] = P.bnd.face[2 * a] == FDTD_FACE_CPML ? P.bnd.cells[2 * a] : 0;
@@ -331,8 +337,8 @@ static void finalize(Plan &P)
     REQUIRE(g.kernel != FDTD_KERNEL_FUSED || P.field_elems * 4 < ((size_t)1 << 32),
             FDTD_E_UNSUPPORTED, "grid too large for one fused plan (field array >= 4 GiB)");
     const size_t Lx = P.lo[0] + P.hi[0], Ly = P.lo[1] + P.hi[1], Lz = P.lo[2] + P.hi[2];
-    const size_t xl = Lx * g.ny * g.nz, yl = (size_t)P.px * Ly * g.nz,
-                 zl = (size_t)P.px * g.ny * Lz;
+    const size_t xl = Lx * g.ny * g.nz, yl = (size_t)g.nx * Ly * g.nz,
+                 zl = (size_t)g.nx * g.ny * Lz;
     const size_t sz[PSI_COUNT] = {yl, zl, zl, xl, xl, yl, yl, zl, zl, xl, xl, yl};
     for (int q = 0; q < PSI_COUNT; ++q) P.psi_elems[q] = sz[q];
     build_coefficients(P);
@@ -1039,8 +1045,7 @@ fdtd_status fdtd_plan_get_config(const fdtd_plan *plan, int32_t *rows, int32_t *
 fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t rows, int32_t zchunk)
 {
     PLAN_GUARD(plan) {
-        REQUIRE(rows == 2 || rows == 4 || rows == 8 || rows == 16,
-                FDTD_E_INVALID_ARG, "tile rows must be 2, 4, 8 or 16");
+        REQUIRE(valid_rows(rows), FDTD_E_INVALID_ARG, "tile rows must be 2, 4, 8, 12 or 16");
         REQUIRE(zchunk >= 1 && zchunk <= 64, FDTD_E_INVALID_ARG, "z-chunk must be in [1, 64]");
         plan->cfg.rows = rows;
         plan->cfg.zchunk = zchunk;

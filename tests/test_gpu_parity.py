@@ -160,7 +160,7 @@ def test_small_microstrip_fp32_matches_oracle(fd, small_ref, fused):
     assert np.max(np.abs(rg["Z0"] / ro["Z0"] - 1)) < 5e-3
 
 
-@pytest.mark.parametrize("rows,zchunk", [(2, 64), (2, 5), (4, 1), (4, 32), (8, 7), (16, 3)])
+@pytest.mark.parametrize("rows,zchunk", [(2, 64), (2, 5), (4, 1), (4, 32), (8, 7), (12, 9), (16, 3)])
 def test_fused_launch_shapes_agree(fd, rows, zchunk):
     """Every tile height and z-chunk (ragged tails in x, y and z) gives the
     same fields as the reference launch shape."""

