@@ -264,6 +264,8 @@ fdtd_status fdtd_batch_get_config(const fdtd_batch *batch, int32_t *tile_rows,
                                   int32_t *zchunk);
 fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t tile_rows, int32_t zchunk);
 
+/* Message of the batch's last failed call; with batch == NULL, of the last
+ * failed fdtd_batch_create on the calling thread. */
 const char *fdtd_batch_last_error(const fdtd_batch *batch);
 void fdtd_batch_destroy(fdtd_batch *batch);
 

@@ -333,7 +333,7 @@ class BatchSimulation:
         arr = (C.c_void_p * len(self.handles))(*[h.value for h in self.handles])
         self.handle = C.c_void_p()
         check(lib().fdtd_batch_create(arr, len(self.handles), C.byref(self.handle)),
-              "fdtd_batch_create")
+              "fdtd_batch_create", None, batch=True)
         if config is not None:
             self.set_config(*config)
         n = C.c_size_t()

@@ -126,7 +126,9 @@ def lib():
 def check(code: int, where: str, handle=None, batch=False):
     if code != FDTD_OK:
         msg = ""
-        if handle:
+        if handle or batch:
+            # a batch call without a handle is fdtd_batch_create: its message
+            # is kept per thread and read with a NULL handle
             fn = lib().fdtd_batch_last_error if batch else lib().fdtd_last_error
             msg = (fn(handle) or b"").decode()
         raise FdtdError(code, where, msg)

@@ -99,8 +99,11 @@ void compute_blocks(Batch &B)
     B.nb_total = nb;
     B.ni_total = ni;
     B.lut_cap = 1;
-    for (const Plan *P : B.plans)
+    B.id_bits = 5;
+    for (const Plan *P : B.plans) {
         B.lut_cap = std::max<int32_t>(B.lut_cap, (int32_t)(P->lut[0].size() / 4));
+        if (P->id_bits != 5) B.id_bits = 8;
+    }
 }
 
 // Upload the instance tables for the current parity of the member plans.
@@ -162,7 +165,7 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
         hipEvent_t e0, e1;
         hcheck(B.timer.slot(e0, e1), "timer");
         // every instance's step, plus sampling of its input level
-        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, B.lut_cap, P0.step, probes,
+        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, B.lut_cap, B.id_bits, P0.step, probes,
                             B.max_probes, sample, s, e0, e1),
                "batch step");
         const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
@@ -271,6 +274,13 @@ using namespace fdtd;
 
 extern "C" {
 
+// Message of the last failed fdtd_batch_create on this thread.
+static std::string &create_error()
+{
+    static thread_local std::string msg;
+    return msg;
+}
+
 fdtd_status fdtd_batch_create(fdtd_plan *const *plans, int32_t n, fdtd_batch **out)
 {
     if (!plans || n < 1 || !out) return FDTD_E_INVALID_ARG;
@@ -292,13 +302,26 @@ fdtd_status fdtd_batch_create(fdtd_plan *const *plans, int32_t n, fdtd_batch **o
         for (int q = 0; q < n; ++q)
             for (int r = q + 1; r < n; ++r)
                 BREQUIRE(plans[q] != plans[r], FDTD_E_INVALID_ARG, "plan listed twice");
+        // one launch reads one id format: if any member needs 32-bit id
+        // words, the others are laid out with them too
+        bool wide = false;
+        for (const Plan *P : b->plans) wide = wide || P->id_bits != 5;
+        if (wide)
+            for (Plan *P : b->plans)
+                if (P->id_bits == 5) {
+                    P->wide_ids = true;
+                    P->finalized = false;
+                    plan_finalize(*P);
+                }
         b->cfg = default_launch(b->plans.data(), b->plans.size());
         compute_blocks(*b);
     });
     if (st != FDTD_OK) {
+        create_error() = b->err;
         delete b;
         return st;
     }
+    create_error().clear();
     *out = b;
     return FDTD_OK;
 }
@@ -451,7 +474,10 @@ fdtd_status fdtd_batch_get_kernel_time(fdtd_batch *batch, double *ms, int64_t *l
     });
 }
 
-const char *fdtd_batch_last_error(const fdtd_batch *batch) { return batch ? batch->err.c_str() : ""; }
+const char *fdtd_batch_last_error(const fdtd_batch *batch)
+{
+    return batch ? batch->err.c_str() : create_error().c_str();
+}
 
 void fdtd_batch_destroy(fdtd_batch *batch)
 {

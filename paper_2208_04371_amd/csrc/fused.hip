@@ -21,6 +21,8 @@
 // same XCD so their halo re-reads hit that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "probe.hpp"
 
@@ -285,11 +287,16 @@ __device__ __forceinline__ void epatch_store(Smem<R> &sm, const EPatch<R> &p, in
     *dst = p.halo;
 }
 
+// The packed edge ids of a cell: IDB bits per component (x lowest), in a
+// 16-bit word for IDB = 5, a 32-bit word for IDB = 8.
+template <int IDB>
+using IdWord = typename std::conditional<IDB == 5, uint16_t, uint32_t>::type;
+
 // What plane k of the own cell (and the halo cell of this thread) needs
 // from HBM besides the E patch; loaded one plane ahead.
 struct PlaneRegs {
     float hx, hy, hz;          // H^{n-1/2} own
-    uint32_t ids;              // edge ids own (x, y, z in bytes 0, 1, 2)
+    uint32_t ids;              // packed edge ids own
     float hhx, hhy, hhz;       // H^{n-1/2} of the halo cell
     Psi6 ph;                   // H auxiliaries of the own cell (boundary tiles)
 };
@@ -310,7 +317,7 @@ struct TileCtx {
 // Loads for plane k: unconditional (lanes without a cell load a clamped
 // one and discard it); only the auxiliaries of boundary tiles depend on the
 // lane.
-template <bool LAYERS>
+template <bool LAYERS, int IDB>
 __device__ __forceinline__ void plane_load(const DevGrid<float> &d, PlaneRegs &r, const TileCtx &t,
                                            int k)
 {
@@ -318,7 +325,7 @@ __device__ __forceinline__ void plane_load(const DevGrid<float> &d, PlaneRegs &r
     r.hx = ldf(d.H[0], c);
     r.hy = ldf(d.H[1], c);
     r.hz = ldf(d.H[2], c);
-    r.ids = gld(static_cast<const uint32_t *>(d.ids[0]),
+    r.ids = (uint32_t)gld(static_cast<const IdWord<IDB> *>(d.ids[0]),
                 (uint32_t)(t.ci + d.nx * (t.cj + d.ny * k)));
     const uint32_t h = (uint32_t)(d.off + t.chi) + t.sy * t.chj + t.sz * k;
     r.hhx = ldf(d.H[0], h);
@@ -347,7 +354,7 @@ struct MarchState {
 // caller alternates the two register sets instead of copying them: a copy
 // would have to wait for the loads in flight.  Past the end of the chunk
 // the prefetches repeat the last plane (cache hits, results unused).
-template <int R, bool LAYERS>
+template <int R, bool LAYERS, int IDB>
 __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm,
                                             const Tabs<R> &tb, const TileCtx &t, int k,
                                             const PlaneRegs &cur, PlaneRegs &nxt, MarchState &m)
@@ -369,7 +376,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
     }
     EPatch<R> pe;
     epatch_load<R>(d, pe, t.x0, t.y0, min(k + 2, t.z1), t.w);
-    plane_load<LAYERS>(d, nxt, t, min(k + 1, t.z1 - 1));
+    plane_load<LAYERS, IDB>(d, nxt, t, min(k + 1, t.z1 - 1));
 
     // lanes without a cell store into the sink
     const uint32_t c = t.own ? (uint32_t)(d.off + t.i) + t.sy * t.j + t.sz * k
@@ -455,9 +462,10 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
                 }
             }
         }
-        const float4 cx = tb.coef(0, cur.ids & 0xffu);
-        const float4 cy = tb.coef(1, (cur.ids >> 8) & 0xffu);
-        const float4 cz = tb.coef(2, (cur.ids >> 16) & 0xffu);
+        constexpr uint32_t IDM = (1u << IDB) - 1u;
+        const float4 cx = tb.coef(0, cur.ids & IDM);
+        const float4 cy = tb.coef(1, (cur.ids >> IDB) & IDM);
+        const float4 cz = tb.coef(2, (cur.ids >> (2 * IDB)) & IDM);
         const float ex = cx.x * sm.e[s0][0][ly][lx] + cx.y * dHz_y - cx.z * dHy_z;
         const float ey = cy.x * sm.e[s0][1][ly][lx] + cy.y * dHx_z - cy.z * dHz_x;
         float ez = cz.x * sm.e[s0][2][ly][lx] + cz.y * dHy_x - cz.z * dHx_y;
@@ -476,7 +484,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
     lds_barrier();
 }
 
-template <int R, bool LAYERS>
+template <int R, bool LAYERS, int IDB>
 __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int zchunk,
                            int64_t level, Smem<R> &sm, const Tabs<R> &tb)
 {
@@ -544,7 +552,7 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     epatch_load<R>(d, pa, x0, y0, z0, tc.w);
     epatch_load<R>(d, pb, x0, y0, z0 + 1, tc.w);
     PlaneRegs ra{}, rb{};
-    plane_load<LAYERS>(d, ra, tc, z0);
+    plane_load<LAYERS, IDB>(d, ra, tc, z0);
     // inputs of H^{n+1/2}(z0-1) at the own cell, needed by E(z0); on the
     // bottom face the E edges it feeds are PEC, so it is not needed there
     const bool pro = z0 > 0;
@@ -596,10 +604,10 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     // odd last plane runs after the loop
     int k = z0;
     for (; k + 1 < tc.z1; k += 2) {
-        march_plane<R, LAYERS>(d, sm, tb, tc, k, ra, rb, m);
-        march_plane<R, LAYERS>(d, sm, tb, tc, k + 1, rb, ra, m);
+        march_plane<R, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
+        march_plane<R, LAYERS, IDB>(d, sm, tb, tc, k + 1, rb, ra, m);
     }
-    if (k < tc.z1) march_plane<R, LAYERS>(d, sm, tb, tc, k, ra, rb, m);
+    if (k < tc.z1) march_plane<R, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
 }
 
 // Block b of n is dispatched to XCD b % 8; give each XCD a contiguous run
@@ -659,8 +667,15 @@ __device__ __forceinline__ void boundary_tile(const TileSet &s, int q, int &tx, 
 // boundary launch the first `nprobe_blocks` blocks sample the probes of the
 // input level (so sampling overlaps the update instead of costing a launch
 // of its own).
+// Occupancy targets: boundary kernels of 8 or more rows need just over 128
+// VGPRs, one more wave per SIMD than they would get (3 -> 4) is worth the
+// few registers spilled; interior kernels hold 6 waves.
 template <int R, bool LAYERS>
+constexpr int min_waves() { return LAYERS ? (R >= 8 ? 4 : 1) : (R >= 4 ? 6 : 1); }
+
+template <int R, bool LAYERS, int IDB>
 __global__ void __launch_bounds__(TW *R)
+__attribute__((amdgpu_waves_per_eu(min_waves<R, LAYERS>(), 8)))
 k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ sets, int ninst,
         int zchunk, int ntiles, int64_t level, const DevProbes *__restrict__ probes,
         int nprobe_blocks, int max_probes, int lut_cap)
@@ -691,30 +706,30 @@ k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ se
     int tx, ty, tz;
     if (LAYERS) boundary_tile(s, tl - s.sb, tx, ty, tz);
     else interior_tile(s, tl - s.si, tx, ty, tz);
-    fused_tile<R, LAYERS>(grids[lo], tx, ty, tz, zchunk, level, sm, tb);
+    fused_tile<R, LAYERS, IDB>(grids[lo], tx, ty, tz, zchunk, level, sm, tb);
 }
 
-template <int R, bool LAYERS>
+template <int R, bool LAYERS, int IDB>
 hipError_t launch_r(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                     int zchunk, int64_t level, const DevProbes *probes, int nprobe_blocks,
                     int max_probes, int lut_cap, hipStream_t s)
 {
-    k_fused<R, LAYERS><<<ntiles + nprobe_blocks, TW * R, tabs_bytes<R>(lut_cap, LAYERS), s>>>(
+    k_fused<R, LAYERS, IDB><<<ntiles + nprobe_blocks, TW * R, tabs_bytes<R>(lut_cap, LAYERS), s>>>(
         g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes, lut_cap);
     return hipGetLastError();
 }
 
-template <bool LAYERS>
+template <bool LAYERS, int IDB>
 hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                         const LaunchCfg &cfg, int64_t level, const DevProbes *probes, int npb,
                         int max_probes, int lut_cap, hipStream_t s)
 {
     switch (cfg.rows) {
-    case 2: return launch_r<2, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 4: return launch_r<4, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 8: return launch_r<8, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 12: return launch_r<12, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 16: return launch_r<16, LAYERS>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 2: return launch_r<2, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 4: return launch_r<4, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 8: return launch_r<8, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 12: return launch_r<12, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 16: return launch_r<16, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -723,21 +738,28 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
 
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
                         int32_t nb, int32_t ni, const LaunchCfg &cfg, int32_t lut_cap,
-                        int64_t level, const DevProbes *probes_dev, int32_t max_probes,
-                        bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                        int32_t id_bits, int64_t level, const DevProbes *probes_dev,
+                        int32_t max_probes, bool sample_input, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1)
 {
     if (!valid_rows(cfg.rows)) return hipErrorInvalidValue;
     if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
+    if (id_bits != 5 && id_bits != 8) return hipErrorInvalidValue;
+    if (id_bits == 5 && lut_cap > 32) return hipErrorInvalidValue;
     const int npb = (sample_input && level >= 1) ? ninst * max_probes : 0;
     if (e0) (void)hipEventRecord(e0, s);
     hipError_t err = hipSuccess;
     // the two classes write disjoint cells and read only the input level
     if (nb + npb > 0)
-        err = launch_class<true>(grids_dev, sets_dev, ninst, nb, cfg, level, probes_dev, npb,
-                                 max_probes, lut_cap, s);
+        err = id_bits == 5 ? launch_class<true, 5>(grids_dev, sets_dev, ninst, nb, cfg, level,
+                                                   probes_dev, npb, max_probes, lut_cap, s)
+                           : launch_class<true, 8>(grids_dev, sets_dev, ninst, nb, cfg, level,
+                                                   probes_dev, npb, max_probes, lut_cap, s);
     if (err == hipSuccess && ni > 0)
-        err = launch_class<false>(grids_dev, sets_dev, ninst, ni, cfg, level, probes_dev, 0,
-                                  max_probes, lut_cap, s);
+        err = id_bits == 5 ? launch_class<false, 5>(grids_dev, sets_dev, ninst, ni, cfg, level,
+                                                    probes_dev, 0, max_probes, lut_cap, s)
+                           : launch_class<false, 8>(grids_dev, sets_dev, ninst, ni, cfg, level,
+                                                    probes_dev, 0, max_probes, lut_cap, s);
     if (e1) (void)hipEventRecord(e1, s);
     return err;
 }

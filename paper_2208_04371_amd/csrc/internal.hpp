@@ -43,7 +43,9 @@ struct DevGrid {
     T *E[3], *H[3];          // fields read this step
     T *Eo[3], *Ho[3];        // fields written this step (== E/H in place)
     const void *ids[3];      // uint8 or uint16 per edge; fused plans: ids[0] holds
-                             // all three as bytes 0..2 of one uint32 per cell
+                             // all three packed in one word per cell (5 bits
+                             // each in a uint16 if at most 32 coefficient
+                             // sets, else 8 bits each in a uint32)
     const T *lut[3];         // per component [id][4] = Ca, Cb/d_first, Cb/d_second, 0
     T *psi[PSI_COUNT];       // auxiliaries read this step
     T *psi_o[PSI_COUNT];     // auxiliaries written this step (== psi in place)
@@ -142,6 +144,8 @@ struct Plan {
     size_t sink = 0;                     // first of 64 write-only elements per field array
     int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int32_t id16 = 0;
+    int32_t id_bits = 8;                 // fused plans: bits per packed id (5 or 8)
+    bool wide_ids = false;               // set by a batch: pack ids in 32 bits regardless
     std::vector<uint16_t> ids[3];
     std::vector<double> lut[3];          // [id][4]
     std::vector<double> prof[3];         // [PR_COUNT][n_axis]
@@ -192,6 +196,7 @@ struct Batch {
     std::vector<TileSet> sets;          // per plan: tile decomposition and first blocks
     int32_t nb_total = 0, ni_total = 0; // boundary / interior tiles of all plans
     int32_t lut_cap = 1;                // largest coefficient table of the plans
+    int32_t id_bits = 8;                // 5 if every plan packs its ids in 16 bits
     int32_t max_probes = 0;
     int32_t max_nf = 0;
     KernelTimer timer;
@@ -219,11 +224,14 @@ hipError_t launch_dft(const DevDft &d, int64_t n_first, int64_t count, hipStream
 // interior launch.  With sample_input the boundary launch also samples every
 // probe of the input level `level` (if level >= 1).
 // lut_cap: LUT entries per component the launch reserves in LDS (at least
-// the largest nlut of the instances, at most 256).
+// the largest nlut of the instances, at most 256).  id_bits: 5 when every
+// instance packs its ids into 16-bit words (at most 32 coefficient sets),
+// else 8 (32-bit words).
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
                         int32_t nb, int32_t ni, const LaunchCfg &cfg, int32_t lut_cap,
-                        int64_t level, const DevProbes *probes_dev, int32_t max_probes,
-                        bool sample_input, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                        int32_t id_bits, int64_t level, const DevProbes *probes_dev,
+                        int32_t max_probes, bool sample_input, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1);
 hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
                               int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
 hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,

@@ -149,6 +149,7 @@ static void build_coefficients(Plan &P)
     REQUIRE(table.size() <= 65536, FDTD_E_UNSUPPORTED,
             "more than 65536 distinct edge coefficients");
     P.id16 = table.size() > 256 ? 1 : 0;
+    P.id_bits = table.size() <= 32 && !P.wide_ids ? 5 : 8;
     const double d[3] = {P.g.dx, P.g.dy, P.g.dz};
     for (int comp = 0; comp < 3; ++comp) {
         // E_comp = Ca E + Cb/d_first * diff_first - Cb/d_second * diff_second,
@@ -260,7 +261,7 @@ static void layout(Plan &P)
     P.r_static.off = 0;
     if (P.g.kernel == FDTD_KERNEL_FUSED) {
         // fused plans: the three ids of a cell packed into one 32-bit word
-        take(P.r_ids[0], P.id_elems * 4);
+        take(P.r_ids[0], P.id_elems * (P.id_bits == 5 ? 2 : 4));
         take(P.r_ids[1], 0);
         take(P.r_ids[2], 0);
     } else {
@@ -505,12 +506,17 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     P.base = base;
     std::vector<std::vector<char>> keep;
     if (P.g.kernel == FDTD_KERNEL_FUSED) {
-        keep.emplace_back(P.id_elems * 4);
-        uint32_t *q = reinterpret_cast<uint32_t *>(keep.back().data());
-        for (size_t t = 0; t < P.id_elems; ++t)
-            q[t] = (uint32_t)P.ids[0][t] | (uint32_t)P.ids[1][t] << 8 |
-                   (uint32_t)P.ids[2][t] << 16;
-        upload(P, P.r_ids[0], q, P.id_elems * 4, s);
+        const int b = P.id_bits;
+        const size_t word = b == 5 ? 2 : 4;
+        keep.emplace_back(P.id_elems * word);
+        char *q = keep.back().data();
+        for (size_t t = 0; t < P.id_elems; ++t) {
+            const uint32_t w = (uint32_t)P.ids[0][t] | (uint32_t)P.ids[1][t] << b |
+                               (uint32_t)P.ids[2][t] << (2 * b);
+            if (word == 2) reinterpret_cast<uint16_t *>(q)[t] = (uint16_t)w;
+            else reinterpret_cast<uint32_t *>(q)[t] = w;
+        }
+        upload(P, P.r_ids[0], q, P.id_elems * word, s);
     }
     for (int c = 0; c < 3; ++c) {
         if (P.g.kernel == FDTD_KERNEL_FUSED) {
@@ -664,7 +670,8 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
             hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
                                    reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF), 1,
                                    P.tiles.nb, P.tiles.ni, P.cfg,
-                                   std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)), P.step,
+                                   std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)),
+                                   P.id_bits, P.step,
                                    reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
                                    P.nprobe(), P.nprobe() > 0, s, e0, e1),
                       "fused step");

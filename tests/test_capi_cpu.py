@@ -127,7 +127,9 @@ def test_workspace_grows_with_ping_pong(fd):
     hf = describe(p, fused=True)
     hp = describe(p, fused=False)
     sf, sp = fdtd_plan_workspace_size(hf), fdtd_plan_workspace_size(hp)
-    assert sf > 1.8 * sp
+    # fields and H auxiliaries are kept twice; E auxiliaries are updated in
+    # place and the ids are packed
+    assert sf > 1.6 * sp
     fdtd_plan_destroy(hf)
     fdtd_plan_destroy(hp)
 

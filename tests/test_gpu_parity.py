@@ -238,6 +238,46 @@ def test_batch_equals_single_runs(fd):
         assert np.array_equal(bs.field(q, W.EZ), s.field(W.EZ)), f"instance {q} Ez"
 
 
+def _many_materials(nmat=4, seed=21, block=(8, 8, 16)):
+    """The small microstrip with its dielectric replaced by blocks of nmat
+    random materials: 54 distinct edge coefficients for the defaults (more
+    than the 32 a 16-bit id word holds), so its ids need 32-bit words."""
+    p = W.small_microstrip(nsteps=120, seed=seed)
+    rng = np.random.default_rng(seed)
+    base = len(p.materials)
+    p.materials += [W.Material(float(e)) for e in rng.uniform(2.0, 12.0, nmat)]
+    nz, ny, nx = p.cells.shape
+    bz, by, bx = block
+    ids = rng.integers(0, nmat, size=(-(-nz // bz), -(-ny // by), -(-nx // bx)))
+    full = np.repeat(np.repeat(np.repeat(ids, bz, 0), by, 1), bx, 2)[:nz, :ny, :nx]
+    sub = p.cells < 2   # keep the strip
+    p.cells[sub] = (base + full[sub]).astype(np.uint8)
+    return p
+
+
+def test_batch_mixed_id_widths(fd):
+    """A member with more than 32 coefficient sets makes the whole batch use
+    32-bit id words; every member still equals its own single run."""
+    probs = [_many_materials(), W.small_microstrip(nsteps=120, seed=6)]
+    bs = fd.BatchSimulation(probs)
+    bs.run(120)
+    for q, p in enumerate(probs):
+        s = fd.Simulation(p, fused=True, config=bs.get_config()).run(120)
+        Vb, Ib = bs.spectra(q)
+        Vs, Is = s.spectra()
+        assert np.array_equal(Vb, Vs) and np.array_equal(Ib, Is), f"instance {q}"
+        for comp in range(6):
+            assert np.array_equal(bs.field(q, comp), s.field(comp)), (q, comp)
+    bs.close()
+
+
+def test_many_materials_fused_matches_oracle(fd):
+    p = _many_materials()
+    sim = fd.Simulation(p, fused=True).run()
+    o = oracle.Oracle(p).run(p.nsteps)
+    _check_fields(sim, o, 1e-4, norm="l2")
+
+
 # ---------------------------------------------------------------------------
 # the 400x120x80 microstrip at full size, in the benchmark's launch shape
 # ---------------------------------------------------------------------------
