@@ -19,6 +19,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -70,8 +71,9 @@ def _rows(d: str, pattern: str):
 
 
 def _kernel_class(name: str) -> str:
-    if "k_fused" in name:
-        return "boundary" if "true>" in name else "interior"
+    m = re.search(r"k_fused<\s*\d+\s*,\s*(true|false)", name)
+    if m:
+        return "boundary" if m.group(1) == "true" else "interior"
     if "k_copy" in name and "tail" not in name:
         return "copy"
     return "other"
