@@ -60,7 +60,7 @@ enum { FDTD_SI = 0, FDTD_NORMALIZED = 1 };          /* NORMALIZED: c = eps0 = mu
 enum { FDTD_KERNEL_PLAIN = 0, FDTD_KERNEL_FUSED = 1 };
 enum { FDTD_FACE_PEC = 0, FDTD_FACE_CPML = 1 };
 enum { FDTD_WAVE_NONE = 0, FDTD_WAVE_GAUSSIAN_STEPS = 1, FDTD_WAVE_GAUSS_SINE = 2,
-       FDTD_WAVE_DIFF_GAUSSIAN = 3 };
+       FDTD_WAVE_DIFF_GAUSSIAN = 3, FDTD_WAVE_SAMPLED = 4 };
 enum { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_HY = 4, FDTD_HZ = 5 };
 
 /* Grid and run options.  The time step is courant / (c sqrt(dx^-2 + dy^-2 +
@@ -116,7 +116,10 @@ typedef struct {
  *   GAUSSIAN_STEPS: s = A exp(-((n+1 - t0)/width)^2), t0 and width in steps;
  *   GAUSS_SINE:     s = A exp(-((t-t0)/tau)^2) sin(2 pi fc (t-t0)),
  *                   tau = 2 sqrt(ln 1000) / (pi bandwidth);
- *   DIFF_GAUSSIAN:  s = A (-2 (t-t0)/width) exp(-((t-t0)/width)^2)  (eq. 3).
+ *   DIFF_GAUSSIAN:  s = A (-2 (t-t0)/width) exp(-((t-t0)/width)^2)  (eq. 3);
+ *   SAMPLED:        s = A samples[n] at level n+1 (0 past the last sample),
+ *                   any pulse given point by point, see
+ *                   fdtd_plan_set_source_samples.
  * t0 <= 0 selects three pulse widths (tau or width). */
 typedef struct {
     int32_t kind;
@@ -155,6 +158,13 @@ fdtd_status fdtd_plan_add_point_probe(fdtd_plan *plan, int32_t comp, int32_t i, 
 /* Set the soft source (see fdtd_source).  Errors: INVALID_ARG for a box
  * outside [0,nx)x[0,ny]x[0,nz) or bad waveform parameters. */
 fdtd_status fdtd_plan_set_source(fdtd_plan *plan, const fdtd_source *src);
+
+/* Samples of a SAMPLED source: samples[m] (FP64, n values, host memory,
+ * copied) is added at E level m + 1.  Before the plan is finalized (the
+ * first fdtd_plan_workspace_size); a plan whose source is SAMPLED cannot be
+ * finalized without them (STATE).  Errors: INVALID_ARG for NULL samples or
+ * n < 1. */
+fdtd_status fdtd_plan_set_source_samples(fdtd_plan *plan, const double *samples, int64_t n);
 
 /* Analysis frequencies (Hz or normalized), nf in [1, 4096]. */
 fdtd_status fdtd_plan_set_frequencies(fdtd_plan *plan, const double *f, int32_t nf);

@@ -71,6 +71,7 @@ class OrProblem(C.Structure):
         ("nport", C.c_int32), ("ports", PI32),
         ("npoint", C.c_int32), ("points", PI32),
         ("nf", C.c_int32), ("freqs", PD),
+        ("src_nsamp", C.c_int64), ("src_samples", PD),
     ]
 
 
@@ -143,6 +144,9 @@ class Oracle:
             pr.src_box = (C.c_int32 * 6)(*s.box)
             pr.src_t0, pr.src_width, pr.src_fc = s.t0, s.width, s.fc
             pr.src_bw, pr.src_amp = s.bandwidth, s.amplitude
+            if getattr(s, "samples", None) is not None:
+                self.src_samples = np.ascontiguousarray(s.samples, dtype=np.float64)
+                pr.src_nsamp, pr.src_samples = len(self.src_samples), _pd(self.src_samples)
         pr.nport, pr.ports = len(p.ports), _pi(ports)
         pr.npoint, pr.points = len(p.points), _pi(points)
         pr.nf, pr.freqs = len(p.freqs), _pd(self.freqs)

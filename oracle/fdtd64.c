@@ -52,7 +52,8 @@ typedef struct {
     int32_t face[6];           /* x-, x+, y-, y+, z-, z+ */
     int32_t pml_cells[6];
     double pml_m, pml_sigma_max, pml_kappa_max, pml_alpha_max;
-    int32_t src_kind;          /* 0 none, 1 Gaussian in steps, 2 Gaussian sine, 3 differential Gaussian */
+    int32_t src_kind;          /* 0 none, 1 Gaussian in steps, 2 Gaussian sine, 3 differential Gaussian,
+                                  4 sampled */
     int32_t src_comp;          /* E component driven (0 Ex, 1 Ey, 2 Ez) */
     int32_t src_box[6];        /* its nodes i0,i1,j0,j1,k0,k1 inclusive */
     double src_t0, src_width, src_fc, src_bw, src_amp;
@@ -62,6 +63,8 @@ typedef struct {
     const int32_t *points;     /* 4 per point: comp, i, j, k */
     int32_t nf;
     const double *freqs;
+    int64_t src_nsamp;         /* sampled source: values for levels 1..src_nsamp */
+    const double *src_samples;
 } or_problem;
 
 /* Every array is allocated by the caller.  Field and auxiliary arrays are
@@ -248,6 +251,8 @@ static double waveform(const or_problem *p, double dt, int64_t level)
         double u = (t - t0) / sg;
         return a * (-2.0 * u) * exp(-u * u);
     }
+    if (p->src_kind == 4)   /* a given pulse: sample m is added at level m + 1 */
+        return (level >= 1 && level <= p->src_nsamp) ? a * p->src_samples[level - 1] : 0.0;
     return 0.0;
 }
 

@@ -80,6 +80,12 @@ def fdtd_plan_set_source(plan, kind, box, t0=0.0, width=0.0, fc=0.0, bandwidth=0
     check(lib().fdtd_plan_set_source(plan, C.byref(s)), "fdtd_plan_set_source", plan)
 
 
+def fdtd_plan_set_source_samples(plan, samples):
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    check(lib().fdtd_plan_set_source_samples(plan, _ptr(s), len(s)),
+          "fdtd_plan_set_source_samples", plan)
+
+
 def fdtd_plan_set_frequencies(plan, freqs):
     f = np.ascontiguousarray(freqs, dtype=np.float64)
     check(lib().fdtd_plan_set_frequencies(plan, _ptr(f), len(f)), "fdtd_plan_set_frequencies", plan)
@@ -256,6 +262,8 @@ def describe(prob, fused: bool = True, precision: Optional[int] = None):
             if s.comp != 2:
                 raise FdtdError(-3, "describe", "the GPU source drives Ez")
             fdtd_plan_set_source(h, s.kind, s.box, s.t0, s.width, s.fc, s.bandwidth, s.amplitude)
+            if getattr(s, "samples", None) is not None:
+                fdtd_plan_set_source_samples(h, s.samples)
         fdtd_plan_set_frequencies(h, prob.freqs)
     except Exception:
         fdtd_plan_destroy(h)

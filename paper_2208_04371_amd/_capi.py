@@ -101,6 +101,7 @@ SIGNATURES = {
     "fdtd_sparams": (I32, [I32, I32, PD, PD, PD, PD, C.c_double, PD, PD, PD, PD, PD]),
     "fdtd_status_string": (C.c_char_p, [I32]),
     "fdtd_device_copy": (I32, [P, P, C.c_size_t, P]),
+    "fdtd_plan_set_source_samples": (I32, [P, C.POINTER(C.c_double), C.c_int64]),
 }
 
 _lib = None

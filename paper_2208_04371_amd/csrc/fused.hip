@@ -25,6 +25,7 @@
 
 #include "internal.hpp"
 #include "probe.hpp"
+#include "source.hpp"
 
 namespace fdtd {
 
@@ -47,24 +48,6 @@ __device__ __forceinline__ bool layer_slot(int p, int lo, int hi, int n, int &s)
     if (p < lo) { s = p; return true; }
     if (p >= n - hi) { s = p - (n - hi) + lo; return true; }
     return false;
-}
-
-__device__ double src_value(const DevGrid<float> &d, int64_t level)
-{
-    if (d.src_kind == FDTD_WAVE_GAUSSIAN_STEPS) {
-        const double u = ((double)level - d.src_t0) / d.src_w;
-        return d.src_amp * exp(-u * u);
-    }
-    const double t = (double)level * d.dt;
-    if (d.src_kind == FDTD_WAVE_GAUSS_SINE) {
-        const double u = (t - d.src_t0) / d.src_tau;
-        return d.src_amp * exp(-u * u) * sin(2.0 * M_PI * d.src_fc * (t - d.src_t0));
-    }
-    if (d.src_kind == FDTD_WAVE_DIFF_GAUSSIAN) {
-        const double u = (t - d.src_t0) / d.src_w;
-        return d.src_amp * (-2.0 * u) * exp(-u * u);
-    }
-    return 0.0;
 }
 
 // Every device array is accessed through the global address space with a
@@ -582,7 +565,7 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     tc.sval = 0.f;
     tc.src_col = d.src_kind != 0 && tc.own && i >= d.src_box[0] && i <= d.src_box[1] &&
                  j >= d.src_box[2] && j <= d.src_box[3];
-    if (tc.src_col) tc.sval = (float)src_value(d, level + 1);
+    if (tc.src_col) tc.sval = (float)source_at(d, level + 1);
     lds_barrier();   // caches visible
 
     MarchState m;

@@ -63,6 +63,8 @@ struct DevGrid {
     int32_t src_kind;
     int32_t src_box[6];
     double src_t0, src_w, src_fc, src_tau, src_amp, dt;
+    const double *src_samples;   // SAMPLED: value for level m + 1 at [m]
+    int64_t src_nsamp;
 };
 
 // Probe tables: every probe is a weighted sum of field samples.
@@ -133,6 +135,7 @@ struct Plan {
     struct Point { int32_t comp, i, j, k; };
     std::vector<Point> points;
     fdtd_source src{};
+    std::vector<double> src_samples;     // SAMPLED source values (level m + 1 at [m])
     std::vector<double> freqs;
 
     // derived at finalize
@@ -159,7 +162,7 @@ struct Plan {
     size_t elt = 4;                      // bytes per field value
 
     // workspace layout (offsets relative to the bound pointer)
-    Region r_ids[3], r_lut[3], r_prof[3], r_toff, r_tcomp, r_tw, r_range, r_freq;
+    Region r_ids[3], r_lut[3], r_prof[3], r_toff, r_tcomp, r_tw, r_range, r_freq, r_src;
     Region r_E[2][3], r_H[2][3], r_psi[2][PSI_COUNT], r_hist, r_acc;
     Region r_grid;                       // fused plans: DevGrid<float> per parity + block start
     Region r_static, r_mut;

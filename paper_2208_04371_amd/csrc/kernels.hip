@@ -13,6 +13,7 @@
 
 #include "internal.hpp"
 #include "probe.hpp"
+#include "source.hpp"
 
 namespace fdtd {
 
@@ -33,26 +34,6 @@ __device__ __forceinline__ int edge_id(const DevGrid<T> &d, int comp, int64_t q)
 {
     return d.id16 ? (int)static_cast<const uint16_t *>(d.ids[comp])[q]
                   : (int)static_cast<const uint8_t *>(d.ids[comp])[q];
-}
-
-// Value of the soft source for the E level `level` (eq. 3 family).
-__device__ double source_value(int kind, double t0, double w, double fc, double tau,
-                               double amp, double dt, int64_t level)
-{
-    if (kind == FDTD_WAVE_GAUSSIAN_STEPS) {
-        double u = ((double)level - t0) / w;
-        return amp * exp(-u * u);
-    }
-    double t = (double)level * dt;
-    if (kind == FDTD_WAVE_GAUSS_SINE) {
-        double u = (t - t0) / tau;
-        return amp * exp(-u * u) * sin(2.0 * M_PI * fc * (t - t0));
-    }
-    if (kind == FDTD_WAVE_DIFF_GAUSSIAN) {
-        double u = (t - t0) / w;
-        return amp * (-2.0 * u) * exp(-u * u);
-    }
-    return 0.0;
 }
 
 // Layer-modified difference: diff * (1/kappa) + psi, psi <- b psi + c diff.
@@ -148,8 +129,7 @@ __global__ void __launch_bounds__(BX *BY) k_e_plain(DevGrid<T> d, int64_t level)
     T ez = cz[0] * d.E[2][c] + cz[1] * dHy_x - cz[2] * dHx_y;
     if (d.src_kind && i >= d.src_box[0] && i <= d.src_box[1] && j >= d.src_box[2] &&
         j <= d.src_box[3] && k >= d.src_box[4] && k <= d.src_box[5]) {
-        ez += (T)source_value(d.src_kind, d.src_t0, d.src_w, d.src_fc, d.src_tau, d.src_amp,
-                              d.dt, level + 1);
+        ez += (T)source_at(d, level + 1);
     }
     d.Eo[2][c] = ez;
 }

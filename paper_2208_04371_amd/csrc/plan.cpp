@@ -274,6 +274,7 @@ static void layout(Plan &P)
     take(P.r_tw, std::max<size_t>(1, P.tw.size()) * 8);
     take(P.r_range, std::max<size_t>(1, P.prange.size()) * 4);
     take(P.r_freq, std::max<size_t>(1, P.freqs.size()) * 8);
+    take(P.r_src, std::max<size_t>(1, P.src_samples.size()) * 8);
     take(P.r_grid, GRID_PROBES_OFF + sizeof(DevProbes) + 64);
     P.r_static.bytes = cur;
     // mutable state
@@ -310,6 +311,8 @@ static void finalize(Plan &P)
     const fdtd_grid &g = P.g;
     REQUIRE(!P.cells.empty(), FDTD_E_STATE, "materials not set");
     REQUIRE(!P.freqs.empty(), FDTD_E_STATE, "frequencies not set");
+    REQUIRE(P.src.kind != FDTD_WAVE_SAMPLED || !P.src_samples.empty(), FDTD_E_STATE,
+            "sampled source without samples");
     const bool norm = g.units == FDTD_NORMALIZED;
     P.c0 = norm ? 1.0 : 299792458.0;
     P.mu0 = norm ? 1.0 : 4.0e-7 * M_PI;
@@ -383,6 +386,8 @@ DevGrid<T> Plan::dev_grid() const
     d.src_kind = src.kind;
     for (int q = 0; q < 6; ++q) d.src_box[q] = src.box[q];
     d.dt = dt;
+    d.src_samples = reinterpret_cast<const double *>(base + r_src.off);
+    d.src_nsamp = (int64_t)src_samples.size();
     d.src_amp = src.amplitude;
     d.src_fc = src.fc;
     d.src_w = src.width;
@@ -537,6 +542,7 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     upload(P, P.r_tw, P.tw.data(), P.tw.size() * 8, s);
     upload(P, P.r_range, P.prange.data(), P.prange.size() * 4, s);
     upload(P, P.r_freq, P.freqs.data(), P.freqs.size() * 8, s);
+    upload(P, P.r_src, P.src_samples.data(), P.src_samples.size() * 8, s);
     if (P.g.kernel == FDTD_KERNEL_FUSED) {
         // launch table of the fused kernel: the descriptors of both buffer
         // parities, the tile decomposition (written before each run whose
@@ -850,7 +856,7 @@ fdtd_status fdtd_plan_set_source(fdtd_plan *plan, const fdtd_source *src)
         NOT_FINAL(P);
         REQUIRE(src, FDTD_E_INVALID_ARG, "null source");
         const fdtd_source &s = *src;
-        REQUIRE(s.kind >= FDTD_WAVE_NONE && s.kind <= FDTD_WAVE_DIFF_GAUSSIAN,
+        REQUIRE(s.kind >= FDTD_WAVE_NONE && s.kind <= FDTD_WAVE_SAMPLED,
                 FDTD_E_INVALID_ARG, "unknown waveform");
         if (s.kind != FDTD_WAVE_NONE) {
             const int *b = s.box;
@@ -859,10 +865,20 @@ fdtd_status fdtd_plan_set_source(fdtd_plan *plan, const fdtd_source *src)
                     FDTD_E_INVALID_ARG, "source box outside the grid");
             if (s.kind == FDTD_WAVE_GAUSS_SINE)
                 REQUIRE(s.bandwidth > 0, FDTD_E_INVALID_ARG, "bandwidth must be positive");
-            else
+            else if (s.kind != FDTD_WAVE_SAMPLED)
                 REQUIRE(s.width > 0, FDTD_E_INVALID_ARG, "pulse width must be positive");
         }
         P.src = s;
+    });
+}
+
+fdtd_status fdtd_plan_set_source_samples(fdtd_plan *plan, const double *samples, int64_t n)
+{
+    PLAN_GUARD(plan) {
+        Plan &P = *plan;
+        NOT_FINAL(P);
+        REQUIRE(samples && n >= 1, FDTD_E_INVALID_ARG, "no source samples");
+        P.src_samples.assign(samples, samples + n);
     });
 }
 

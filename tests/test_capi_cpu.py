@@ -191,3 +191,23 @@ def test_device_copy_validates_arguments(fd):
     assert L.fdtd_device_copy(C.c_void_p(4096), C.c_void_p(8192 + 8), 64, None) == -1
     assert L.fdtd_device_copy(C.c_void_p(4096), C.c_void_p(8192), 60, None) == -1
     assert L.fdtd_device_copy(C.c_void_p(4096), C.c_void_p(4096 + 32), 64, None) == -1
+
+
+def test_source_samples_validation(fd):
+    import dataclasses
+    from paper_2208_04371_amd import describe, fdtd_plan_destroy, fdtd_plan_workspace_size
+    p = W.small_microstrip(nsteps=10)
+    # a SAMPLED source without samples cannot be finalized
+    ps = dataclasses.replace(p, source=dataclasses.replace(p.source, kind=W.SAMPLED))
+    h = describe(ps, fused=True)
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_workspace_size(h)
+    assert e.value.code == -2
+    L = fd.lib()
+    assert L.fdtd_plan_set_source_samples(h, None, 5) == -1
+    fdtd_plan_destroy(h)
+    # with samples it finalizes
+    ps = dataclasses.replace(ps, source=dataclasses.replace(ps.source, samples=np.ones(8)))
+    h = describe(ps, fused=True)
+    assert fdtd_plan_workspace_size(h) > 0
+    fdtd_plan_destroy(h)

@@ -238,6 +238,31 @@ def test_batch_equals_single_runs(fd):
         assert np.array_equal(bs.field(q, W.EZ), s.field(W.EZ)), f"instance {q} Ez"
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_sampled_and_eq3_sources_match_oracle(fd, fused):
+    """A pulse given point by point (SAMPLED) and the differential Gaussian
+    of eq. 3 drive the GPU grid as they drive the oracle."""
+    import dataclasses
+    p = W.small_microstrip(nsteps=300, fp32=fused)
+    box = p.source.box
+    dt = oracle.Oracle(p).dt
+    rng = np.random.default_rng(31)
+    srcs = [W.Source(W.SAMPLED, box, samples=rng.standard_normal(250) * np.hanning(250)),
+            W.Source(W.DIFF_GAUSSIAN, box, width=40 * dt)]
+    for src in srcs:
+        q = dataclasses.replace(p, source=src)
+        sim = fd.Simulation(q, fused=fused).run()
+        o = oracle.Oracle(q).run(q.nsteps)
+        _say(f"source kind {src.kind} fused={fused}")
+        if fused:
+            _check_fields(sim, o, 1e-4, norm="l2")
+        else:
+            _check_fields(sim, o, 1e-10)
+        Vg, _ = sim.spectra()
+        Vo, _ = o.spectra()
+        assert _rel(Vg, Vo) < (1e-4 if fused else 1e-10)
+
+
 def _many_materials(nmat=4, seed=21, block=(8, 8, 16)):
     """The small microstrip with its dielectric replaced by blocks of nmat
     random materials: 54 distinct edge coefficients for the defaults (more

@@ -454,3 +454,26 @@ def test_tangential_e_vanishes_on_pec_and_absorbing_faces():
     q = _tem_line(1, 2)                     # magnetic walls normal to x
     oq = oracle.Oracle(q).run(300)
     assert np.max(np.abs(oq.field(W.EZ)[:q.nz, :, 0])) > 1e-3
+
+
+def test_sampled_source_reproduces_the_analytic_pulse():
+    """A source given point by point (value m at level m + 1) drives the grid
+    exactly as the analytic pulse it samples; past the last sample it adds
+    nothing."""
+    import dataclasses
+    p = W.small_microstrip(nsteps=120, fp32=False)
+    ref = oracle.Oracle(p)
+    vals = ref.waveform(1, 80)            # levels 1..80 of the Gaussian sine
+    assert np.max(np.abs(vals)) > 0
+    ps = dataclasses.replace(p, source=dataclasses.replace(p.source, kind=W.SAMPLED,
+                                                           samples=vals))
+    o = oracle.Oracle(ps)
+    got = o.waveform(1, 100)
+    assert np.array_equal(got[:80], vals) and np.all(got[80:] == 0)
+    # the analytic pulse truncated after level 80 drives the same fields
+    ref_t = oracle.Oracle(dataclasses.replace(ps, nsteps=80))
+    ref_t.run(80)
+    o.run(80)
+    ref.run(80)
+    for c in range(6):
+        assert np.array_equal(o.field(c), ref.field(c)), c

@@ -22,7 +22,7 @@ import numpy as np
 # boundary kinds per face, faces ordered x-, x+, y-, y+, z-, z+
 PEC, CPML, PMC = 0, 1, 2
 # waveform kinds
-GAUSSIAN_STEPS, GAUSS_SINE, DIFF_GAUSSIAN = 1, 2, 3
+GAUSSIAN_STEPS, GAUSS_SINE, DIFF_GAUSSIAN, SAMPLED = 1, 2, 3, 4
 # field components
 EX, EY, EZ, HX, HY, HZ = 0, 1, 2, 3, 4, 5
 
@@ -80,6 +80,7 @@ class Source:
     bandwidth: float = 0.0
     amplitude: float = 1.0
     comp: int = EZ
+    samples: Optional[np.ndarray] = None   # SAMPLED: value m added at level m + 1
 
 
 @dataclass
@@ -394,7 +395,7 @@ def window(p: Problem, box: Tuple[int, int, int, int, int, int], name: str = "")
             clipped += [c0 - lo[a], c1 - lo[a]]
         if all(clipped[2 * a] <= clipped[2 * a + 1] for a in range(3)):
             src = Source(s.kind, tuple(clipped), s.t0, s.width, s.fc, s.bandwidth, s.amplitude,
-                         s.comp)
+                         s.comp, s.samples)
     return Problem(
         name=name or f"{p.name}_window", nx=x1 - x0, ny=y1 - y0, nz=z1 - z0, dx=p.dx, dy=p.dy,
         dz=p.dz, courant=p.courant, normalized=p.normalized,
