@@ -261,7 +261,9 @@ fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
  * cache_path (may be NULL) names a JSON file keyed by GPU architecture and
  * member grid shapes: a hit applies the stored choice without timing
  * (*best_index = -1), a miss stores the winner.  Synchronous.  *best_index
- * receives the index of the chosen candidate in rows-major order. */
+ * receives the index of the chosen candidate in rows-major order.  On a
+ * failure the launch shape is the last one tried and the member states are
+ * undefined until fdtd_batch_reset. */
 fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,
                                 void *stream, int32_t *best_index);
 
@@ -282,6 +284,16 @@ void fdtd_batch_destroy(fdtd_batch *batch);
 /* Launch configuration of a single FUSED plan (same meaning as for a batch). */
 fdtd_status fdtd_plan_get_config(const fdtd_plan *plan, int32_t *tile_rows, int32_t *zchunk);
 fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t tile_rows, int32_t zchunk);
+
+/* fdtd_batch_autotune for one bound FUSED plan that is not in a batch: the
+ * same candidates, timing and cache (a plan and a one-member batch of the
+ * same grid shape share a cache entry).  The plan is reset afterwards unless
+ * the shape came from the cache.  STATE if unbound or in a batch,
+ * UNSUPPORTED for the plain kernels, INVALID_ARG for trial_steps < 1.  On a
+ * failure the launch shape is the last one tried and the state is undefined
+ * until fdtd_reset.  Synchronous. */
+fdtd_status fdtd_plan_autotune(fdtd_plan *plan, int32_t trial_steps, const char *cache_path,
+                               void *stream, int32_t *best_index);
 
 /* ---- kernel timing ----------------------------------------------------- */
 

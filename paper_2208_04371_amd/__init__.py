@@ -169,6 +169,15 @@ def fdtd_plan_get_config(plan):
     return r.value, z.value
 
 
+def fdtd_plan_autotune(plan, trial_steps: int = 20, cache_path: Optional[str] = None,
+                       stream=None) -> int:
+    best = C.c_int32()
+    path = cache_path.encode() if cache_path else None
+    check(lib().fdtd_plan_autotune(plan, trial_steps, path, _stream(stream), C.byref(best)),
+          "fdtd_plan_autotune", plan)
+    return best.value
+
+
 def fdtd_plan_set_timing(plan, enable: bool):
     check(lib().fdtd_plan_set_timing(plan, 1 if enable else 0), "fdtd_plan_set_timing", plan)
 
@@ -293,6 +302,12 @@ class Simulation:
 
     def reset(self):
         fdtd_reset(self.handle)
+
+    def autotune(self, trial_steps: int = 20, cache_path: Optional[str] = None) -> int:
+        return fdtd_plan_autotune(self.handle, trial_steps, cache_path)
+
+    def get_config(self):
+        return fdtd_plan_get_config(self.handle)
 
     @property
     def step(self) -> int:

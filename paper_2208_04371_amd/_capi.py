@@ -94,6 +94,7 @@ SIGNATURES = {
     "fdtd_batch_destroy": (None, [P]),
     "fdtd_plan_get_config": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
     "fdtd_plan_set_config": (I32, [P, I32, I32]),
+    "fdtd_plan_autotune": (I32, [P, I32, C.c_char_p, P, C.POINTER(I32)]),
     "fdtd_plan_set_timing": (I32, [P, I32]),
     "fdtd_plan_get_kernel_time": (I32, [P, PD, C.POINTER(I64)]),
     "fdtd_batch_set_timing": (I32, [P, I32]),

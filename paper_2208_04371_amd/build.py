@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfdtd.so")
-SOURCES = ["plan.cpp", "batch.cpp", "post.cpp", "kernels.hip", "fused.hip", "copy.hip"]
+SOURCES = ["plan.cpp", "batch.cpp", "tune.cpp", "post.cpp", "kernels.hip", "fused.hip", "copy.hip"]
 ARCH = os.environ.get("FDTD_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

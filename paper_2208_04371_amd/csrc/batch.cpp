@@ -184,89 +184,6 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
     batch_flush(B, s);
 }
 
-// ---- autotuner -------------------------------------------------------------
-// Candidates: tile rows x z-chunk (1 << 20 = a whole column per block).
-const int TUNE_ROWS[] = {2, 4, 8, 12, 16};
-const int TUNE_Z[] = {4, 8, 16, 32, 64};
-
-// Key: the shapes of the member grids, in order.
-std::string cache_key(const Batch &B)
-{
-    std::string k;
-    for (const Plan *P : B.plans) {
-        char buf[64];
-        std::snprintf(buf, sizeof buf, "%dx%dx%d;", P->g.nx, P->g.ny, P->g.nz);
-        k += buf;
-    }
-    return k;
-}
-
-std::string device_name()
-{
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return "unknown";
-    return prop.gcnArchName;
-}
-
-// The cache is a JSON object written one entry per line:
-//   {
-//   "gfx950:...|400x120x80;": [4, 32, 0.0312],
-//   ...
-//   }
-// (rows, z-chunk, milliseconds per step).  Unknown lines are ignored.
-std::vector<std::pair<std::string, std::string>> cache_read(const char *path)
-{
-    std::vector<std::pair<std::string, std::string>> out;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return out;
-    char line[4096];
-    while (std::fgets(line, sizeof line, f)) {
-        std::string s(line);
-        const size_t q0 = s.find('"'), q1 = s.find("\": [");
-        const size_t b1 = s.find(']');
-        if (q0 == std::string::npos || q1 == std::string::npos || b1 == std::string::npos) continue;
-        out.emplace_back(s.substr(q0 + 1, q1 - q0 - 1), s.substr(q1 + 4, b1 - q1 - 4));
-    }
-    std::fclose(f);
-    return out;
-}
-
-bool cache_lookup(const char *path, const std::string &key, int &rows, int &z)
-{
-    for (const auto &e : cache_read(path)) {
-        if (e.first != key) continue;
-        double ms = 0;
-        if (std::sscanf(e.second.c_str(), "%d , %d , %lf", &rows, &z, &ms) >= 2) {
-            const bool ok_rows = valid_rows(rows);
-            return ok_rows && z >= 1 && z <= 64;
-        }
-    }
-    return false;
-}
-
-void cache_store(const char *path, const std::string &key, int rows, int z, double ms)
-{
-    auto entries = cache_read(path);
-    char val[128];
-    std::snprintf(val, sizeof val, "%d, %d, %.6g", rows, z, ms);
-    bool found = false;
-    for (auto &e : entries)
-        if (e.first == key) { e.second = val; found = true; }
-    if (!found) entries.emplace_back(key, val);
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE *f = std::fopen(tmp.c_str(), "w");
-    if (!f) return;
-    std::fprintf(f, "{\n");
-    for (size_t q = 0; q < entries.size(); ++q)
-        std::fprintf(f, "\"%s\": [%s]%s\n", entries[q].first.c_str(), entries[q].second.c_str(),
-                     q + 1 < entries.size() ? "," : "");
-    std::fprintf(f, "}\n");
-    std::fclose(f);
-    std::rename(tmp.c_str(), path);
-}
-
 }  // namespace
 }  // namespace fdtd
 
@@ -409,47 +326,21 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
         BREQUIRE(B.bound, FDTD_E_STATE, "batch not bound");
         BREQUIRE(trial_steps >= 1, FDTD_E_INVALID_ARG, "trial_steps must be >= 1");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const std::string key = device_name() + "|" + cache_key(B);
-        int cached_rows = 0, cached_z = 0;
-        if (cache_path && cache_lookup(cache_path, key, cached_rows, cached_z)) {
-            B.cfg.rows = cached_rows;
-            B.cfg.zchunk = cached_z;
+        const std::string key = tune_device_name() + "|" + tune_shape_key(B.plans.data(), B.plans.size());
+        TimerPause pause(B.timer);   // trial launches are not the caller's
+        TuneHooks h;
+        h.apply = [&](const LaunchCfg &c) {
+            B.cfg = c;
             upload_tables(B, s);
-            if (best_index) *best_index = -1;
-            return;
+        };
+        h.run = [&](int32_t n) { batch_run(B, n, s); };
+        LaunchCfg best = B.cfg;
+        int32_t best_i = -1;
+        hcheck(tune_search(h, trial_steps, cache_path, key, s, best, best_i), "autotune");
+        if (best_i >= 0) {
+            for (Plan *P : B.plans) plan_reset(*P, s);
+            hcheck(hipStreamSynchronize(s), "sync");
         }
-        hipEvent_t a, b;
-        hcheck(hipEventCreate(&a), "event");
-        hcheck(hipEventCreate(&b), "event");
-        const LaunchCfg keep = B.cfg;
-        const bool keep_timing = B.timer.on;
-        B.timer.on = false;
-        float best = 1e30f;
-        int best_i = -1, idx = 0;
-        LaunchCfg best_cfg = keep;
-        for (int r : TUNE_ROWS)
-            for (int z : TUNE_Z) {
-                B.cfg.rows = r;
-                B.cfg.zchunk = z;
-                upload_tables(B, s);
-                batch_run(B, 1, s);   // warm-up
-                hcheck(hipEventRecord(a, s), "event");
-                batch_run(B, trial_steps, s);
-                hcheck(hipEventRecord(b, s), "event");
-                hcheck(hipEventSynchronize(b), "event sync");
-                float ms = 0;
-                hcheck(hipEventElapsedTime(&ms, a, b), "event time");
-                if (ms < best) { best = ms; best_i = idx; best_cfg = B.cfg; }
-                ++idx;
-            }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        B.timer.on = keep_timing;
-        B.cfg = best_cfg;
-        upload_tables(B, s);
-        for (Plan *P : B.plans) plan_reset(*P, s);
-        hcheck(hipStreamSynchronize(s), "sync");
-        if (cache_path) cache_store(cache_path, key, best_cfg.rows, best_cfg.zchunk, best / trial_steps);
         if (best_index) *best_index = best_i;
     });
 }

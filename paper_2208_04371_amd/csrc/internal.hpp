@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -126,6 +127,16 @@ struct KernelTimer {
     void destroy();
 };
 
+// Keeps launches out of a timer for a scope (restored also when it unwinds).
+struct TimerPause {
+    KernelTimer &t;
+    bool keep;
+    explicit TimerPause(KernelTimer &k) : t(k), keep(k.on) { t.on = false; }
+    ~TimerPause() { t.on = keep; }
+    TimerPause(const TimerPause &) = delete;
+    TimerPause &operator=(const TimerPause &) = delete;
+};
+
 struct Plan {
     fdtd_grid g{};
     std::vector<uint8_t> cells;
@@ -243,6 +254,23 @@ hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_pr
 TileSet make_tileset(const Plan &P, const LaunchCfg &cfg);
 // Default launch shape for one step of the given grids.
 LaunchCfg default_launch(const Plan *const *plans, size_t n);
+
+// Launch-shape search.  apply() installs a shape, run(n) enqueues n steps on
+// the stream being timed; both throw on failure.
+struct TuneHooks {
+    std::function<void(const LaunchCfg &)> apply;
+    std::function<void(int32_t)> run;
+};
+// GPU architecture name of the current device (the cache key's first part).
+std::string tune_device_name();
+// "NXxNYxNZ;" per grid, in order (the cache key's second part).
+std::string tune_shape_key(const Plan *const *plans, size_t n);
+// Times every candidate shape for trial_steps steps after one warm-up step
+// and applies the fastest; with cache_path, a stored shape for key is applied
+// instead (best_index = -1) and a timed winner is stored.  best_index is the
+// winner's position in rows-major candidate order.
+hipError_t tune_search(const TuneHooks &h, int32_t trial_steps, const char *cache_path,
+                       const std::string &key, hipStream_t s, LaunchCfg &best_cfg, int32_t &best_index);
 
 }  // namespace fdtd
 

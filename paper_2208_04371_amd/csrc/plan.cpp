@@ -1075,6 +1075,34 @@ fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t rows, int32_t zchunk)
     });
 }
 
+fdtd_status fdtd_plan_autotune(fdtd_plan *plan, int32_t trial_steps, const char *cache_path,
+                               void *stream, int32_t *best_index)
+{
+    PLAN_GUARD(plan) {
+        Plan &P = *plan;
+        REQUIRE(P.bound, FDTD_E_STATE, "plan not bound");
+        REQUIRE(!P.in_batch, FDTD_E_STATE, "plan belongs to a batch; use fdtd_batch_autotune");
+        REQUIRE(P.g.kernel == FDTD_KERNEL_FUSED, FDTD_E_UNSUPPORTED,
+                "only the fused kernel has a launch shape to tune");
+        REQUIRE(trial_steps >= 1, FDTD_E_INVALID_ARG, "trial_steps must be >= 1");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const Plan *self = &P;
+        const std::string key = tune_device_name() + "|" + tune_shape_key(&self, 1);
+        TimerPause pause(P.timer);   // trial launches are not the caller's
+        TuneHooks h;
+        h.apply = [&](const LaunchCfg &c) { P.cfg = c; };
+        h.run = [&](int32_t n) { run_plan(P, n, s); };
+        LaunchCfg best = P.cfg;
+        int32_t best_i = -1;
+        hip_check(tune_search(h, trial_steps, cache_path, key, s, best, best_i), "autotune");
+        if (best_i >= 0) {
+            reset_plan(P, s);
+            hip_check(hipStreamSynchronize(s), "sync");
+        }
+        if (best_index) *best_index = best_i;
+    });
+}
+
 fdtd_status fdtd_plan_set_timing(fdtd_plan *plan, int32_t enable)
 {
     PLAN_GUARD(plan) {

@@ -1,5 +1,6 @@
-"""Launch-shape autotuner of batches (the tile height x z-chunk search with
-its JSON cache keyed by GPU architecture and member shapes)."""
+"""Launch-shape autotuner of batches and single fused plans (the tile height
+x z-chunk search with its JSON cache keyed by GPU architecture and grid
+shapes)."""
 import json
 import os
 
@@ -56,4 +57,41 @@ def test_autotune_picks_caches_and_resets(fd, tmp_path):
     assert again.autotune(trial_steps=3, cache_path=cache) == -1
     assert again.get_config() == (rows, z)
     for x in (bs, ref, again):
+        x.close()
+
+
+def test_plan_autotune_picks_caches_and_resets(fd, tmp_path):
+    cache = str(tmp_path / "tune.json")
+    p = W.small_microstrip(nsteps=60, ny=40, seed=5)
+    sim = fd.Simulation(p, fused=True)
+    sim.run(7)                       # the search starts from any state
+    best = sim.autotune(trial_steps=3, cache_path=cache)
+    rows, z = sim.get_config()
+    print("plan autotune picked", best, rows, z, flush=True)
+    assert 0 <= best < 25
+    assert rows in (2, 4, 8, 12, 16) and z in (4, 8, 16, 32, 64)
+    assert sim.step == 0
+    with open(cache) as f:
+        entries = json.load(f)
+    (key, val), = entries.items()
+    assert key.endswith("|96x40x28;")
+    assert val[:2] == [rows, z] and val[2] > 0
+    # the plan was reset: a run now equals a fresh plan in that shape
+    sim.run()
+    ref = fd.Simulation(p, fused=True, config=(rows, z))
+    ref.run()
+    assert np.array_equal(sim.field(W.EZ), ref.field(W.EZ))
+    Va, Ia = sim.spectra()
+    Vb, Ib = ref.spectra()
+    assert np.array_equal(Va, Vb) and np.array_equal(Ia, Ib)
+    # a one-member batch of the same shape shares the cache entry
+    bs = fd.BatchSimulation([p])
+    assert bs.autotune(trial_steps=3, cache_path=cache) == -1
+    assert bs.get_config() == (rows, z)
+    # plain kernels have no launch shape to tune
+    plain = fd.Simulation(p, fused=False)
+    with pytest.raises(fd.FdtdError) as e:
+        plain.autotune(trial_steps=3)
+    assert e.value.code == -3
+    for x in (sim, ref, bs, plain):
         x.close()

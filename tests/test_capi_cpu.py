@@ -66,14 +66,17 @@ def test_create_rejects_bad_grids(fd):
 
 
 def test_call_order_and_argument_errors(fd):
-    from paper_2208_04371_amd import (describe, fdtd_plan_add_port, fdtd_plan_create,
-                                      fdtd_plan_destroy, fdtd_plan_workspace_size, fdtd_run,
-                                      fdtd_plan_set_materials)
+    from paper_2208_04371_amd import (describe, fdtd_plan_add_port, fdtd_plan_autotune,
+                                      fdtd_plan_create, fdtd_plan_destroy,
+                                      fdtd_plan_workspace_size, fdtd_run, fdtd_plan_set_materials)
     p = W.small_microstrip()
     h = describe(p)
-    # run before bind
+    # run or autotune before bind
     with pytest.raises(fd.FdtdError) as e:
         fdtd_run(h, 10, stream=0)
+    assert e.value.code == -2
+    with pytest.raises(fd.FdtdError) as e:
+        fdtd_plan_autotune(h, 3, stream=0)
     assert e.value.code == -2
     # port whose current loop would leave the grid
     h2 = fdtd_plan_create(20, 20, 20, 1, 1, 1, 0.9, units=fd.NORMALIZED)
