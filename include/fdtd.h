@@ -255,13 +255,15 @@ fdtd_status fdtd_batch_reset(fdtd_batch *batch, void *stream);
 /* Advance every member plan by nsteps steps in lockstep.  Asynchronous. */
 fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 
-/* Choose the tile height (2, 4, 8, 12, 16 rows) and z-chunk (4, 8, 16, 32, 64
- * planes) of the batched kernel by timing each candidate
+/* Choose the tile height (2, 4, 8, 12, 16 rows), z-chunk (4, 8, 16, 32, 64
+ * planes) and tile order (0 or 16, see fdtd_batch_set_tile_order) of the
+ * batched kernel by timing each candidate
  * for `trial_steps` steps; the member states are reset afterwards.
  * cache_path (may be NULL) names a JSON file keyed by GPU architecture and
  * member grid shapes: a hit applies the stored choice without timing
  * (*best_index = -1), a miss stores the winner.  Synchronous.  *best_index
- * receives the index of the chosen candidate in rows-major order.  On a
+ * receives the index of the chosen candidate in (rows, z-chunk, order)
+ * lexicographic order (50 candidates).  On a
  * failure the launch shape is the last one tried and the member states are
  * undefined until fdtd_batch_reset. */
 fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,
@@ -270,11 +272,23 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
 /* Launch configuration of the fused kernel: tile rows per block (2, 4, 8,
  * 12 or 16; a block is 64 x rows threads) and the number of z planes one block
  * marches through (1..64).  set returns INVALID_ARG for other values.  The
- * default (at creation) is 8 rows and the longest z-chunk of 32, 16, 8 or 4
+ * default (at creation) is 8 rows and the longest z-chunk of 16, 8 or 4
  * planes that still yields at least 2048 tiles. */
 fdtd_status fdtd_batch_get_config(const fdtd_batch *batch, int32_t *tile_rows,
                                   int32_t *zchunk);
 fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t tile_rows, int32_t zchunk);
+
+/* Order in which the blocks of a fused launch take their tiles.  The GPU
+ * deals blocks to its 8 XCDs (each with its own L2) in turn.  0: each XCD
+ * takes one contiguous run of the tiles, so neighbouring tiles share its L2
+ * (best while the state fits the 256 MB memory-side cache); k in [1, 4096]:
+ * runs of k tiles go to the XCDs in turn, so all XCDs stream one region of
+ * the grid at a time (better once the state streams from HBM); -1
+ * (default): automatic, 0 for a workspace of at most 256 MiB, else 16.  The
+ * order changes timing only, never results.  get returns the setting and
+ * the order launches use (*used, from the workspace size once known). */
+fdtd_status fdtd_batch_set_tile_order(fdtd_batch *batch, int32_t order);
+fdtd_status fdtd_batch_get_tile_order(const fdtd_batch *batch, int32_t *order, int32_t *used);
 
 /* Message of the batch's last failed call; with batch == NULL, of the last
  * failed fdtd_batch_create on the calling thread. */
@@ -284,6 +298,8 @@ void fdtd_batch_destroy(fdtd_batch *batch);
 /* Launch configuration of a single FUSED plan (same meaning as for a batch). */
 fdtd_status fdtd_plan_get_config(const fdtd_plan *plan, int32_t *tile_rows, int32_t *zchunk);
 fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t tile_rows, int32_t zchunk);
+fdtd_status fdtd_plan_set_tile_order(fdtd_plan *plan, int32_t order);
+fdtd_status fdtd_plan_get_tile_order(const fdtd_plan *plan, int32_t *order, int32_t *used);
 
 /* fdtd_batch_autotune for one bound FUSED plan that is not in a batch: the
  * same candidates, timing and cache (a plan and a one-member batch of the

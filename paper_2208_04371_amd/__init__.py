@@ -169,6 +169,17 @@ def fdtd_plan_get_config(plan):
     return r.value, z.value
 
 
+def fdtd_plan_set_tile_order(plan, order: int):
+    check(lib().fdtd_plan_set_tile_order(plan, order), "fdtd_plan_set_tile_order", plan)
+
+
+def fdtd_plan_get_tile_order(plan):
+    o, u = C.c_int32(), C.c_int32()
+    check(lib().fdtd_plan_get_tile_order(plan, C.byref(o), C.byref(u)),
+          "fdtd_plan_get_tile_order", plan)
+    return o.value, u.value
+
+
 def fdtd_plan_autotune(plan, trial_steps: int = 20, cache_path: Optional[str] = None,
                        stream=None) -> int:
     best = C.c_int32()
@@ -306,6 +317,12 @@ class Simulation:
     def autotune(self, trial_steps: int = 20, cache_path: Optional[str] = None) -> int:
         return fdtd_plan_autotune(self.handle, trial_steps, cache_path)
 
+    def set_tile_order(self, order: int):
+        fdtd_plan_set_tile_order(self.handle, order)
+
+    def tile_order(self):
+        return fdtd_plan_get_tile_order(self.handle)
+
     def get_config(self):
         return fdtd_plan_get_config(self.handle)
 
@@ -380,6 +397,16 @@ class BatchSimulation:
     def set_config(self, rows: int, zchunk: int):
         check(lib().fdtd_batch_set_config(self.handle, rows, zchunk), "fdtd_batch_set_config",
               self.handle, batch=True)
+
+    def set_tile_order(self, order: int):
+        check(lib().fdtd_batch_set_tile_order(self.handle, order), "fdtd_batch_set_tile_order",
+              self.handle, batch=True)
+
+    def tile_order(self):
+        o, u = C.c_int32(), C.c_int32()
+        check(lib().fdtd_batch_get_tile_order(self.handle, C.byref(o), C.byref(u)),
+              "fdtd_batch_get_tile_order", self.handle, batch=True)
+        return o.value, u.value
 
     def get_config(self):
         r, z = C.c_int32(), C.c_int32()

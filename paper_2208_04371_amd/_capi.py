@@ -95,6 +95,10 @@ SIGNATURES = {
     "fdtd_plan_get_config": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
     "fdtd_plan_set_config": (I32, [P, I32, I32]),
     "fdtd_plan_autotune": (I32, [P, I32, C.c_char_p, P, C.POINTER(I32)]),
+    "fdtd_plan_set_tile_order": (I32, [P, I32]),
+    "fdtd_plan_get_tile_order": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
+    "fdtd_batch_set_tile_order": (I32, [P, I32]),
+    "fdtd_batch_get_tile_order": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
     "fdtd_plan_set_timing": (I32, [P, I32]),
     "fdtd_plan_get_kernel_time": (I32, [P, PD, C.POINTER(I64)]),
     "fdtd_batch_set_timing": (I32, [P, I32]),

@@ -160,12 +160,14 @@ void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
     const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes);
     Plan &P0 = *B.plans[0];
     const bool sample = B.max_probes > 0;
+    LaunchCfg cfg = B.cfg;
+    cfg.order = tile_order(B.cfg, B.ws_bytes);
     for (int64_t q = 0; q < nsteps; ++q) {
         const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
         hipEvent_t e0, e1;
         hcheck(B.timer.slot(e0, e1), "timer");
         // every instance's step, plus sampling of its input level
-        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, B.cfg, B.lut_cap, B.id_bits, P0.step, probes,
+        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, cfg, B.lut_cap, B.id_bits, P0.step, probes,
                             B.max_probes, sample, s, e0, e1),
                "batch step");
         const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
@@ -315,6 +317,23 @@ fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t rows, int32_t zchun
         compute_blocks(*batch);
         if (batch->bound) upload_tables(*batch, nullptr);
     });
+}
+
+fdtd_status fdtd_batch_set_tile_order(fdtd_batch *batch, int32_t order)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        BREQUIRE(valid_order(order), FDTD_E_INVALID_ARG, "tile order must be -1 or in [0, 4096]");
+        batch->cfg.order = order;
+    });
+}
+
+fdtd_status fdtd_batch_get_tile_order(const fdtd_batch *batch, int32_t *order, int32_t *used)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    if (order) *order = batch->cfg.order;
+    if (used) *used = tile_order(batch->cfg, batch->ws_bytes);
+    return FDTD_OK;
 }
 
 fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,

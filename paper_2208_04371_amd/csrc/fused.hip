@@ -1,8 +1,9 @@
 // Fused FP32 Yee step: H^{n+1/2} and E^{n+1} (with the absorbing-layer
 // auxiliaries and the soft source) in one pass over the grid.
 //
-// A block owns a tile of 64 (x) by R (y) cells and marches through a chunk of
-// z planes.  For plane k it needs E^n of planes k and k+1 with a one-cell
+// A block of 64 x R threads owns a tile of 64 (x) by R (y) cells, or in the
+// last x column of a grid whose width leaves a remainder of at most 32, a
+// narrow tile of 16 by 4R cells, and marches through a chunk of z planes.  For plane k it needs E^n of planes k and k+1 with a one-cell
 // halo in x and y: three E planes rotate through LDS (k and k+1 in use, k+2
 // being filled from registers loaded one iteration earlier).  H^{n+1/2}(k)
 // is computed for the tile plus the low-x column and low-y row (the halo the
@@ -32,6 +33,7 @@ namespace fdtd {
 namespace {
 
 constexpr int TW = 64;        // tile width in x = one wavefront
+constexpr int NW = 16;        // width of the narrow tiles of a ragged last column
 constexpr int LUT_LDS = 256;  // coefficient sets per component (8-bit ids)
 
 // Block barrier that orders LDS accesses only: outstanding global loads
@@ -144,40 +146,53 @@ struct HDiff {
 
 constexpr int ZMAX = 64;   // longest z-chunk (its profiles are cached in LDS)
 
-template <int R>
+// LDS of a tile of X columns by Y rows.
+template <int X, int Y>
 struct Smem {
-    float e[3][3][R + 2][TW + 2];   // 3 rotating E^n planes: rows y0-1..y0+R, cols x0-1..x0+64
-    float h[3][R + 1][TW + 1];      // H^{n+1/2}(k): rows y0-1..y0+R-1, cols x0-1..x0+63
+    float e[3][3][Y + 2][X + 2];    // 3 rotating E^n planes: rows y0-1..y0+Y, cols x0-1..x0+X
+    float h[3][Y + 1][X + 1];       // H^{n+1/2}(k): rows y0-1..y0+Y-1, cols x0-1..x0+X-1
     float dummy[TW];                // target of the writes of repeated items
 };
 
 // The block's tables in the dynamic part of LDS, sized per launch: the
 // coefficient LUTs ([3][cap] entries) and, in boundary launches, the layer
 // profiles of the tile.
-template <int R>
+template <int X, int Y>
 struct Tabs {
     float4 *lut;
-    float *px, *py, *pz;            // [PR_COUNT][TW+2] at x0-1.., [PR_COUNT][R+2] at y0-1..,
+    float *px, *py, *pz;            // [PR_COUNT][X+2] at x0-1.., [PR_COUNT][Y+2] at y0-1..,
     int cap;                        // [PR_COUNT][ZMAX+1] at z0-1..
     __device__ float4 coef(int c, uint32_t id) const { return lut[c * cap + (int)id]; }
-    __device__ float prx(int tab, int p) const { return px[tab * (TW + 2) + p]; }
-    __device__ float pry(int tab, int p) const { return py[tab * (R + 2) + p]; }
+    __device__ float prx(int tab, int p) const { return px[tab * (X + 2) + p]; }
+    __device__ float pry(int tab, int p) const { return py[tab * (Y + 2) + p]; }
     __device__ float prz(int tab, int p) const { return pz[tab * (ZMAX + 1) + p]; }
+    __device__ void place(float4 *dyn, int lut_cap)
+    {
+        cap = lut_cap;
+        lut = dyn;
+        px = reinterpret_cast<float *>(dyn + 3 * lut_cap);
+        py = px + PR_COUNT * (X + 2);
+        pz = py + PR_COUNT * (Y + 2);
+    }
 };
 
+// Dynamic LDS of a launch: the LUTs, and in boundary launches the profiles
+// of the larger of the two tile shapes.
 template <int R>
 constexpr size_t tabs_bytes(int cap, bool layers)
 {
+    constexpr int xy = (TW + 2 + R + 2) > (NW + 2 + TW * R / NW + 2) ? (TW + 2 + R + 2)
+                                                                      : (NW + 2 + TW * R / NW + 2);
     return (size_t)cap * 3 * sizeof(float4) +
-           (layers ? (size_t)PR_COUNT * (TW + 2 + R + 2 + ZMAX + 1) * sizeof(float) : 0);
+           (layers ? (size_t)PR_COUNT * (xy + ZMAX + 1) * sizeof(float) : 0);
 }
 
 // H^{n+1/2} from H^{n-1/2} and the six forward differences of E^n at the
 // LDS-cache positions (lx, ly, lz) of the block.  Inside the layers (LAYERS
 // kernels only) the differences take their auxiliaries; with `store` the
 // updated auxiliaries of the H components are written.
-template <int R, bool LAYERS>
-__device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Tabs<R> &tb,
+template <int X, int Y, bool LAYERS>
+__device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Tabs<X, Y> &tb,
                                         const LayerPos &L, int lx, int ly, int lz, HDiff df,
                                         const Psi6 &ps, bool store, float hx, float hy, float hz,
                                         float &ox, float &oy, float &oz)
@@ -211,18 +226,20 @@ __device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Tabs<R> &
     oz = hz - d.ch[0] * df.ey_x + d.ch[1] * df.ex_y;
 }
 
-// The E^n patch of one plane: rows y0-1 .. y0+R (R+2) of the three
-// components over columns x0 .. x0+63, and the halo columns x0-1, x0+64.
-// Wave w loads row w of each component (rows 0..R-1), NX more row loads
-// from the six remaining (component, row R or R+1) items, and one halo
-// value per lane.  Every wave issues the same loads: items past the last
-// repeat it and land in a dummy LDS row, so no load sits behind a branch
-// (a branch around a load makes the compiler wait for every load and store
-// in flight).
-template <int R>
+// The E^n patch of one plane: rows y0-1 .. y0+Y (Y+2) of the three
+// components over columns x0 .. x0+X-1, and the halo columns x0-1, x0+X.
+// The threads of row group g (X consecutive threads; one wave in 64-wide
+// tiles) load row g of each component (rows 0..Y-1), NX more row loads from
+// the six remaining (component, row Y or Y+1) items, and one halo value per
+// thread.  Every wave issues the same loads: items past the last repeat it
+// and land in a dummy LDS row, so no load sits behind a branch (a branch
+// around a load makes the compiler wait for every load and store in flight).
+// Narrow tiles clamp their rows to the top guard row: their Y can run past
+// the end of the array, and rows beyond the grid only feed discarded cells.
+template <int X, int Y>
 struct EPatch {
-    static constexpr int NX = (6 + R - 1) / R;       // extra row loads per wave
-    static constexpr int NHALO = 6 * (R + 2);        // 2 sides x 3 comps x rows
+    static constexpr int NX = (6 + Y - 1) / Y;       // extra row loads per row group
+    static constexpr int NHALO = 6 * (Y + 2);        // 2 sides x 3 comps x rows
     float v[3];
     float x[NX];
     float halo;
@@ -233,40 +250,51 @@ __device__ __forceinline__ const float *comp_ptr(const float *c0, int64_t stride
     return reinterpret_cast<const float *>(reinterpret_cast<const char *>(c0) + c * stride);
 }
 
-template <int R>
-__device__ __forceinline__ void epatch_load(const DevGrid<float> &d, EPatch<R> &p, int x0, int y0,
-                                            int k, int w)
+// Patch row of a load (see EPatch).
+template <int X>
+__device__ __forceinline__ int patch_row(const DevGrid<float> &d, int y0, int row)
 {
-    const int t = threadIdx.x, lane = t & (TW - 1);
-    const uint32_t base = (uint32_t)(d.off + x0 + d.px * (y0 - 1) + d.px * d.py * k);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p.v[c] = ldf(d.E[c], base + d.px * w + lane);
-#pragma unroll
-    for (int q = 0; q < EPatch<R>::NX; ++q) {
-        const int e = min(w * EPatch<R>::NX + q, 5);          // uniform per wave
-        p.x[q] = ldf(comp_ptr(d.E[0], d.cstride, e >> 1), base + d.px * (R + (e & 1)) + lane);
-    }
-    const int tt = min(t, EPatch<R>::NHALO - 1);
-    const int side = tt & 1, rest = tt >> 1;
-    const int c = rest / (R + 2), row = rest % (R + 2);
-    p.halo = ldf(comp_ptr(d.E[0], d.cstride, c), base + d.px * row + (side ? TW : 0) - (side ? 0 : 1));
+    if constexpr (X < TW) return min(row, d.ny + 1 - y0);
+    else return row;
 }
 
-template <int R>
-__device__ __forceinline__ void epatch_store(Smem<R> &sm, const EPatch<R> &p, int slot, int w)
+template <int X, int Y>
+__device__ __forceinline__ void epatch_load(const DevGrid<float> &d, EPatch<X, Y> &p, int x0, int y0,
+                                            int k, int g, int gx)
+{
+    const int t = threadIdx.x;
+    const uint32_t base = (uint32_t)(d.off + x0 + d.px * (y0 - 1) + d.px * d.py * k);
+    const int vr = patch_row<X>(d, y0, g);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.v[c] = ldf(d.E[c], base + d.px * vr + gx);
+#pragma unroll
+    for (int q = 0; q < EPatch<X, Y>::NX; ++q) {
+        const int e = min(g * EPatch<X, Y>::NX + q, 5);      // uniform per wave if X = 64
+        const int xr = patch_row<X>(d, y0, Y + (e & 1));
+        p.x[q] = ldf(comp_ptr(d.E[0], d.cstride, e >> 1), base + d.px * xr + gx);
+    }
+    const int tt = min(t, EPatch<X, Y>::NHALO - 1);
+    const int side = tt & 1, rest = tt >> 1;
+    const int c = rest / (Y + 2), row = patch_row<X>(d, y0, rest % (Y + 2));
+    p.halo = ldf(comp_ptr(d.E[0], d.cstride, c), base + d.px * row + (side ? X : 0) - (side ? 0 : 1));
+}
+
+template <int X, int Y>
+__device__ __forceinline__ void epatch_store(Smem<X, Y> &sm, const EPatch<X, Y> &p, int slot, int g,
+                                             int gx)
 {
     const int t = threadIdx.x, lane = t & (TW - 1);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sm.e[slot][c][w][lane + 1] = p.v[c];
+    for (int c = 0; c < 3; ++c) sm.e[slot][c][g][gx + 1] = p.v[c];
 #pragma unroll
-    for (int q = 0; q < EPatch<R>::NX; ++q) {
-        const int e = w * EPatch<R>::NX + q;
-        float *dst = e < 6 ? &sm.e[slot][e >> 1][R + (e & 1)][lane + 1] : &sm.dummy[lane];
+    for (int q = 0; q < EPatch<X, Y>::NX; ++q) {
+        const int e = g * EPatch<X, Y>::NX + q;
+        float *dst = e < 6 ? &sm.e[slot][e >> 1][Y + (e & 1)][gx + 1] : &sm.dummy[lane];
         *dst = p.x[q];
     }
     const int side = t & 1, rest = t >> 1;
-    const int c = rest / (R + 2), row = rest % (R + 2);
-    float *dst = t < EPatch<R>::NHALO ? &sm.e[slot][c][row][side ? TW + 1 : 0] : &sm.dummy[lane];
+    const int c = rest / (Y + 2), row = rest % (Y + 2);
+    float *dst = t < EPatch<X, Y>::NHALO ? &sm.e[slot][c][row][side ? X + 1 : 0] : &sm.dummy[lane];
     *dst = p.halo;
 }
 
@@ -287,7 +315,8 @@ struct PlaneRegs {
 // Per-thread constants of one tile.
 struct TileCtx {
     int x0, y0, z0, z1;
-    int w;                     // wave index (uniform)
+    int g;                     // row group: tile row of the thread (uniform per
+                               // wave in 64-wide tiles)
     int i, j, lx, ly;          // own cell and its LDS position
     int ci, cj;                // own cell clamped into the grid (load address)
     int hi_, hj_, hlx, hly;    // halo cell and its LDS position
@@ -337,9 +366,9 @@ struct MarchState {
 // caller alternates the two register sets instead of copying them: a copy
 // would have to wait for the loads in flight.  Past the end of the chunk
 // the prefetches repeat the last plane (cache hits, results unused).
-template <int R, bool LAYERS, int IDB>
-__device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm,
-                                            const Tabs<R> &tb, const TileCtx &t, int k,
+template <int X, int Y, bool LAYERS, int IDB>
+__device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<X, Y> &sm,
+                                            const Tabs<X, Y> &tb, const TileCtx &t, int k,
                                             const PlaneRegs &cur, PlaneRegs &nxt, MarchState &m)
 {
     const int lx = t.lx, ly = t.ly, hlx = t.hlx, hly = t.hly, lane = threadIdx.x & (TW - 1);
@@ -357,8 +386,8 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
             load_psi_h(d, Lh, ph_halo);
         }
     }
-    EPatch<R> pe;
-    epatch_load<R>(d, pe, t.x0, t.y0, min(k + 2, t.z1), t.w);
+    EPatch<X, Y> pe;
+    epatch_load<X, Y>(d, pe, t.x0, t.y0, min(k + 2, t.z1), t.g, lx - 1);
     plane_load<LAYERS, IDB>(d, nxt, t, min(k + 1, t.z1 - 1));
 
     // lanes without a cell store into the sink
@@ -376,7 +405,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
         df.ex_y = sm.e[s0][0][ly + 1][lx] - ex;
         float ox = 0.f, oy = 0.f, oz = 0.f;
         if (!LAYERS || t.own)
-            h_apply<R, LAYERS>(d, tb, L, lx, ly, lz, df, cur.ph, true, cur.hx, cur.hy, cur.hz,
+            h_apply<X, Y, LAYERS>(d, tb, L, lx, ly, lz, df, cur.ph, true, cur.hx, cur.hy, cur.hz,
                                ox, oy, oz);
         stf(d.Ho[0], c, ox);
         stf(d.Ho[1], c, oy);
@@ -397,7 +426,7 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
         df.ey_x = sm.e[s0][1][hly][hlx + 1] - ey;
         df.ex_y = sm.e[s0][0][hly + 1][hlx] - ex;
         float ox, oy, oz;
-        h_apply<R, LAYERS>(d, tb, Lh, hlx, hly, lz, df, ph_halo, false, cur.hhx, cur.hhy,
+        h_apply<X, Y, LAYERS>(d, tb, Lh, hlx, hly, lz, df, ph_halo, false, cur.hhx, cur.hhy,
                            cur.hhz, ox, oy, oz);
         // halo cells outside the grid only feed PEC edges: keep them zero
         const bool live = t.halo_live;
@@ -460,27 +489,29 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<R> &sm
         m.hy_prev = hy;
     }
     // ---- rotate: plane k+2 into the LDS slot plane k leaves ----------------
-    epatch_store<R>(sm, pe, s2, t.w);
+    epatch_store<X, Y>(sm, pe, s2, t.g, lx - 1);
     m.s0 = s1;
     m.s1 = s2;
     m.s2 = s0;
     lds_barrier();
 }
 
-template <int R, bool LAYERS, int IDB>
-__device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int zchunk,
-                           int64_t level, Smem<R> &sm, const Tabs<R> &tb)
+// The tile of X by Y cells at (x0, y0), z-chunk tz.
+template <int X, int Y, bool LAYERS, int IDB>
+__device__ void fused_tile(const DevGrid<float> &d, int x0, int y0, int tz, int zchunk,
+                           int64_t level, Smem<X, Y> &sm, const Tabs<X, Y> &tb)
 {
+    constexpr int NT = X * Y;   // threads of the block
     TileCtx tc;
-    tc.x0 = tx * TW;
-    tc.y0 = ty * R;
+    tc.x0 = x0;
+    tc.y0 = y0;
     tc.z0 = tz * zchunk;
     tc.z1 = min(tc.z0 + zchunk, d.nz);
-    const int x0 = tc.x0, y0 = tc.y0, z0 = tc.z0;
+    const int z0 = tc.z0;
     const int t = threadIdx.x;
-    const int lane = t & (TW - 1), row = t / TW;
-    tc.w = __builtin_amdgcn_readfirstlane(row);
-    const int i = x0 + lane, j = y0 + row;
+    const int col = t % X, row = t / X;
+    tc.g = X == TW ? __builtin_amdgcn_readfirstlane(row) : row;
+    const int i = x0 + col, j = y0 + row;
     tc.i = i;
     tc.j = j;
     tc.ci = min(i, d.nx - 1);
@@ -488,17 +519,17 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     tc.own = i < d.nx && j < d.ny;
     tc.sy = (uint32_t)d.px;
     tc.sz = (uint32_t)(d.px * d.py);
-    tc.lx = lane + 1;
+    tc.lx = col + 1;
     tc.ly = row + 1;
     const int lx = tc.lx, ly = tc.ly;
 
     // the halo cell this thread recomputes H for: the low-y row, then the
     // low-x column; the other threads repeat the last one (writing to a
     // dummy LDS row) so that the halo work has no branch either
-    const int nh = TW + R + 1;
+    const int nh = X + Y + 1;
     const int th = min(t, nh - 1);
-    const int hi_ = th < TW ? x0 + th : x0 - 1;
-    const int hj_ = th < TW ? y0 - 1 : y0 - 1 + (th - TW);
+    const int hi_ = th < X ? x0 + th : x0 - 1;
+    const int hj_ = th < X ? y0 - 1 : y0 - 1 + (th - X);
     tc.halo_thread = t < nh;
     // only halo cells inside the grid matter: the others feed PEC edges only
     tc.halo_live = hi_ >= 0 && hj_ >= 0 && hi_ < d.nx && hj_ < d.ny;
@@ -511,29 +542,29 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
 
     // ---- block caches: LUTs (and the layer profiles of boundary tiles) ------
     const int nlut = d.nlut;
-    for (int q = t; q < 3 * nlut; q += TW * R) {
+    for (int q = t; q < 3 * nlut; q += NT) {
         const int c = q / nlut, e = q % nlut;
         tb.lut[c * tb.cap + e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
     }
     if constexpr (LAYERS) {
-        for (int q = t; q < PR_COUNT * (TW + 2); q += TW * R) {
-            const int tab = q / (TW + 2), p = q % (TW + 2);
+        for (int q = t; q < PR_COUNT * (X + 2); q += NT) {
+            const int tab = q / (X + 2), p = q % (X + 2);
             tb.px[q] = prof_at(d.prof[0], tab, d.nx, x0 - 1 + p);
         }
-        for (int q = t; q < PR_COUNT * (R + 2); q += TW * R) {
-            const int tab = q / (R + 2), p = q % (R + 2);
+        for (int q = t; q < PR_COUNT * (Y + 2); q += NT) {
+            const int tab = q / (Y + 2), p = q % (Y + 2);
             tb.py[q] = prof_at(d.prof[1], tab, d.ny, y0 - 1 + p);
         }
-        for (int q = t; q < PR_COUNT * (ZMAX + 1); q += TW * R) {
+        for (int q = t; q < PR_COUNT * (ZMAX + 1); q += NT) {
             const int tab = q / (ZMAX + 1), p = q % (ZMAX + 1);
             tb.pz[q] = prof_at(d.prof[2], tab, d.nz, z0 - 1 + p);
         }
     }
 
     // ---- prologue: request everything the first plane needs at once -------
-    EPatch<R> pa, pb;
-    epatch_load<R>(d, pa, x0, y0, z0, tc.w);
-    epatch_load<R>(d, pb, x0, y0, z0 + 1, tc.w);
+    EPatch<X, Y> pa, pb;
+    epatch_load<X, Y>(d, pa, x0, y0, z0, tc.g, col);
+    epatch_load<X, Y>(d, pb, x0, y0, z0 + 1, tc.g, col);
     PlaneRegs ra{}, rb{};
     plane_load<LAYERS, IDB>(d, ra, tc, z0);
     // inputs of H^{n+1/2}(z0-1) at the own cell, needed by E(z0); on the
@@ -573,11 +604,11 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     m.hy_prev = 0.f;
     if (pro) {
         float oz;
-        h_apply<R, LAYERS>(d, tb, pL, lx, ly, 0, pdf, pps, false, phx, phy, phz, m.hx_prev,
+        h_apply<X, Y, LAYERS>(d, tb, pL, lx, ly, 0, pdf, pps, false, phx, phy, phz, m.hx_prev,
                            m.hy_prev, oz);
     }
-    epatch_store<R>(sm, pa, 0, tc.w);
-    epatch_store<R>(sm, pb, 1, tc.w);
+    epatch_store<X, Y>(sm, pa, 0, tc.g, col);
+    epatch_store<X, Y>(sm, pb, 1, tc.g, col);
     lds_barrier();
 
     m.s0 = 0;
@@ -587,19 +618,25 @@ __device__ void fused_tile(const DevGrid<float> &d, int tx, int ty, int tz, int 
     // odd last plane runs after the loop
     int k = z0;
     for (; k + 1 < tc.z1; k += 2) {
-        march_plane<R, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
-        march_plane<R, LAYERS, IDB>(d, sm, tb, tc, k + 1, rb, ra, m);
+        march_plane<X, Y, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
+        march_plane<X, Y, LAYERS, IDB>(d, sm, tb, tc, k + 1, rb, ra, m);
     }
-    if (k < tc.z1) march_plane<R, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
+    if (k < tc.z1) march_plane<X, Y, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
 }
 
-// Block b of n is dispatched to XCD b % 8; give each XCD a contiguous run
-// of tiles so that neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int n)
+// Tile of block b of n.  Block b is dispatched to XCD b % 8.  Order 0: each
+// XCD gets one contiguous run of tiles, so neighbouring tiles share its L2.
+// Order k >= 1: runs of k tiles are dealt to the XCDs in turn; blocks past
+// the last whole round of 8k take the tile of their own index.
+__device__ __forceinline__ int xcd_tile(int b, int n, int order)
 {
     const int xcd = b & 7, idx = b >> 3;
-    const int q = n >> 3, r = n & 7;
-    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
+    if (order == 0) {
+        const int q = n >> 3, r = n & 7;
+        return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
+    }
+    const int whole = n / (8 * order) * (8 * order);
+    return b >= whole ? b : ((idx / order) * 8 + xcd) * order + idx % order;
 }
 
 // Tile q of the interior box, x fastest.
@@ -611,9 +648,11 @@ __device__ __forceinline__ void interior_tile(const TileSet &s, int q, int &tx, 
     tz = s.iz0 + q / (nx * ny);
 }
 
-// Tile q of the complement of the interior box: whole xy-planes of tiles
-// outside [iz0, iz1) first, then whole x-rows outside [iy0, iy1) of the
-// planes inside, then the tiles outside [ix0, ix1) of the rows inside.
+// Tile q of the complement of the interior box among the 64-wide tiles:
+// whole xy-planes of tiles outside [iz0, iz1) first, then whole x-rows
+// outside [iy0, iy1) of the planes inside, then the tiles outside [ix0, ix1)
+// of the rows inside.  (The narrow tiles of a ragged last column are
+// interleaved with these in the boundary launch.)
 __device__ __forceinline__ void boundary_tile(const TileSet &s, int q, int &tx, int &ty, int &tz)
 {
     const int nix = s.ix1 - s.ix0, niy = s.iy1 - s.iy0, niz = s.iz1 - s.iz0;
@@ -661,24 +700,22 @@ __global__ void __launch_bounds__(TW *R)
 __attribute__((amdgpu_waves_per_eu(min_waves<R, LAYERS>(), 8)))
 k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ sets, int ninst,
         int zchunk, int ntiles, int64_t level, const DevProbes *__restrict__ probes,
-        int nprobe_blocks, int max_probes, int lut_cap)
+        int nprobe_blocks, int max_probes, int lut_cap, int order)
 {
-    __shared__ Smem<R> sm;
+    constexpr int YN = TW * R / NW;   // rows of a narrow tile
+    using SmW = Smem<TW, R>;
+    using SmN = Smem<NW, YN>;
+    constexpr size_t SMB = LAYERS && sizeof(SmN) > sizeof(SmW) ? sizeof(SmN) : sizeof(SmW);
+    __shared__ __attribute__((aligned(16))) char smraw[SMB];
     extern __shared__ float4 dyn_lds[];
-    Tabs<R> tb;
-    tb.cap = lut_cap;
-    tb.lut = dyn_lds;
-    tb.px = reinterpret_cast<float *>(dyn_lds + 3 * lut_cap);
-    tb.py = tb.px + PR_COUNT * (TW + 2);
-    tb.pz = tb.py + PR_COUNT * (R + 2);
     const int b = blockIdx.x;
     if (b < nprobe_blocks) {
         const int inst = b / max_probes, q = b % max_probes;
         if (q < probes[inst].nprobe)
-            probe_one(grids[inst], probes[inst], q, level, reinterpret_cast<double *>(&sm));
+            probe_one(grids[inst], probes[inst], q, level, reinterpret_cast<double *>(smraw));
         return;
     }
-    const int tl = xcd_tile(b - nprobe_blocks, ntiles);
+    const int tl = xcd_tile(b - nprobe_blocks, ntiles, order);
     int lo = 0, hi = ninst - 1;
     while (lo < hi) {          // last instance whose first block <= tl
         const int mid = (lo + hi + 1) >> 1;
@@ -687,18 +724,39 @@ k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ se
     }
     const TileSet s = sets[lo];
     int tx, ty, tz;
-    if (LAYERS) boundary_tile(s, tl - s.sb, tx, ty, tz);
-    else interior_tile(s, tl - s.si, tx, ty, tz);
-    fused_tile<R, LAYERS, IDB>(grids[lo], tx, ty, tz, zchunk, level, sm, tb);
+    if constexpr (LAYERS) {
+        // the narrow tiles sit at every st-th position of the grid's range,
+        // spread over all XCDs
+        int q = tl - s.sb;
+        const int nn = s.nxw * s.nty * s.tz;
+        const int st = nn > 0 ? s.nb / nn : 1;
+        const int before = min(q / st + 1, nn);         // narrow positions <= q
+        if (nn > 0 && q % st == 0 && q / st < nn) {
+            const int n = q / st, sub = n % s.nxw, rest = n / s.nxw;
+            Tabs<NW, YN> tb;
+            tb.place(dyn_lds, lut_cap);
+            fused_tile<NW, YN, true, IDB>(grids[lo], s.tx * TW + sub * NW, (rest % s.nty) * YN,
+                                          rest / s.nty, zchunk, level,
+                                          *reinterpret_cast<SmN *>(smraw), tb);
+            return;
+        }
+        boundary_tile(s, nn > 0 ? q - before : q, tx, ty, tz);
+    } else {
+        interior_tile(s, tl - s.si, tx, ty, tz);
+    }
+    Tabs<TW, R> tb;
+    tb.place(dyn_lds, lut_cap);
+    fused_tile<TW, R, LAYERS, IDB>(grids[lo], tx * TW, ty * R, tz, zchunk, level,
+                                   *reinterpret_cast<SmW *>(smraw), tb);
 }
 
 template <int R, bool LAYERS, int IDB>
 hipError_t launch_r(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                     int zchunk, int64_t level, const DevProbes *probes, int nprobe_blocks,
-                    int max_probes, int lut_cap, hipStream_t s)
+                    int max_probes, int lut_cap, int order, hipStream_t s)
 {
     k_fused<R, LAYERS, IDB><<<ntiles + nprobe_blocks, TW * R, tabs_bytes<R>(lut_cap, LAYERS), s>>>(
-        g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes, lut_cap);
+        g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes, lut_cap, order);
     return hipGetLastError();
 }
 
@@ -708,11 +766,11 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
                         int max_probes, int lut_cap, hipStream_t s)
 {
     switch (cfg.rows) {
-    case 2: return launch_r<2, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 4: return launch_r<4, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 8: return launch_r<8, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 12: return launch_r<12, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
-    case 16: return launch_r<16, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, s);
+    case 2: return launch_r<2, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 4: return launch_r<4, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 8: return launch_r<8, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 12: return launch_r<12, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 16: return launch_r<16, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -725,7 +783,7 @@ hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev
                         int32_t max_probes, bool sample_input, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1)
 {
-    if (!valid_rows(cfg.rows)) return hipErrorInvalidValue;
+    if (!valid_rows(cfg.rows) || cfg.order < 0 || !valid_order(cfg.order)) return hipErrorInvalidValue;
     if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
     if (id_bits != 5 && id_bits != 8) return hipErrorInvalidValue;
     if (id_bits == 5 && lut_cap > 32) return hipErrorInvalidValue;

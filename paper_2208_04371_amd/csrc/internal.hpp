@@ -82,7 +82,21 @@ struct DevProbes {
 struct LaunchCfg {
     int32_t rows = 4;        // tile rows (y) per block of the fused kernel
     int32_t zchunk = 32;     // planes marched per block
+    int32_t order = -1;      // block-to-tile order (see tile_order), -1 = automatic
 };
+
+// Blocks are dispatched to the 8 XCDs in turn.  Order 0 hands each XCD one
+// contiguous run of tiles (neighbours share its L2: best while the state
+// stays in the 256 MB memory-side cache); order k >= 1 deals runs of k
+// tiles to the XCDs in turn (all XCDs work on one region of the grid at a
+// time: better once the state streams from HBM).  Automatic: 0 up to that
+// cache size, else 16.
+constexpr size_t MALL_BYTES = (size_t)256 << 20;
+inline int32_t tile_order(const LaunchCfg &c, size_t state_bytes)
+{
+    return c.order >= 0 ? c.order : (state_bytes <= MALL_BYTES ? 0 : 16);
+}
+inline bool valid_order(int32_t order) { return order >= -1 && order <= 4096; }
 
 // Tile heights the fused kernel is instantiated for.
 inline bool valid_rows(int32_t rows)
@@ -96,11 +110,16 @@ inline bool valid_rows(int32_t rows)
 // absorbing layer form a box [ix0, ix1) x [iy0, iy1) x [iz0, iz1) of tile
 // indices (the condition is separable per axis); they run through the
 // interior kernel, the others through the boundary kernel.
+// A ragged last x column of at most 32 cells is covered by nxw narrow
+// tiles of 16 x 4R cells per (row of narrow tiles, z-chunk) instead of one
+// mostly empty 64-wide tile; they run in the boundary launch, interleaved
+// with the 64-wide boundary tiles.
 struct TileSet {
-    int32_t tx, ty, tz;               // tiles per axis
+    int32_t tx, ty, tz;               // 64-wide tiles per axis
     int32_t ix0, ix1, iy0, iy1, iz0, iz1;
-    int32_t nb, ni;                   // boundary / interior tiles
+    int32_t nb, ni;                   // boundary (incl. narrow) / interior tiles
     int32_t sb, si;                   // first block of this grid in each launch
+    int32_t nxw, nty;                 // narrow sub-columns (0..2), narrow tile rows
 };
 
 // ---------------------------------------------------------------------------
@@ -268,7 +287,7 @@ std::string tune_shape_key(const Plan *const *plans, size_t n);
 // Times every candidate shape for trial_steps steps after one warm-up step
 // and applies the fastest; with cache_path, a stored shape for key is applied
 // instead (best_index = -1) and a timed winner is stored.  best_index is the
-// winner's position in rows-major candidate order.
+// winner's position in (rows, z-chunk, order) lexicographic candidate order.
 hipError_t tune_search(const TuneHooks &h, int32_t trial_steps, const char *cache_path,
                        const std::string &key, hipStream_t s, LaunchCfg &best_cfg, int32_t &best_index);
 

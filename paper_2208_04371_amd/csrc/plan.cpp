@@ -406,11 +406,11 @@ template DevGrid<double> Plan::dev_grid<double>() const;
 
 LaunchCfg default_launch(const Plan *const *plans, size_t n)
 {
-    // 8-row tiles, and the longest z-chunk (32, 16, 8 or 4 planes) that
-    // still gives each of the 256 CUs about 8 tiles
+    // 8-row tiles, and the longest z-chunk (16, 8 or 4 planes) that still
+    // gives each of the 256 CUs about 8 tiles
     LaunchCfg c;
     c.rows = 8;
-    for (c.zchunk = 32; c.zchunk > 4; c.zchunk /= 2) {
+    for (c.zchunk = 16; c.zchunk > 4; c.zchunk /= 2) {
         int64_t tiles = 0;
         for (size_t q = 0; q < n; ++q) {
             const fdtd_grid &g = plans[q]->g;
@@ -426,10 +426,15 @@ TileSet make_tileset(const Plan &P, const LaunchCfg &cfg)
     TileSet t{};
     const int n[3] = {P.g.nx, P.g.ny, P.g.nz};
     const int w[3] = {64, cfg.rows, cfg.zchunk};
+    // a last x column of 1..32 cells goes to 16-wide tiles
+    const int rx = P.g.nx % 64;
+    t.nxw = (rx > 0 && rx <= 32) ? (rx + 15) / 16 : 0;
+    t.nty = (P.g.ny + 4 * cfg.rows - 1) / (4 * cfg.rows);
     int cnt[3], b0[3], b1[3];
     bool empty = false;
     for (int a = 0; a < 3; ++a) {
         cnt[a] = (n[a] + w[a] - 1) / w[a];
+        if (a == 0 && t.nxw > 0) cnt[a] = n[a] / 64;
         b0[a] = b1[a] = 0;
         int first = -1, last = -1;
         for (int q = 0; q < cnt[a]; ++q) {
@@ -451,7 +456,7 @@ TileSet make_tileset(const Plan &P, const LaunchCfg &cfg)
     t.iy0 = b0[1]; t.iy1 = b1[1];
     t.iz0 = b0[2]; t.iz1 = b1[2];
     t.ni = (b1[0] - b0[0]) * (b1[1] - b0[1]) * (b1[2] - b0[2]);
-    t.nb = cnt[0] * cnt[1] * cnt[2] - t.ni;
+    t.nb = cnt[0] * cnt[1] * cnt[2] - t.ni + t.nxw * t.nty * cnt[2];
     return t;
 }
 
@@ -673,9 +678,11 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
         if (fused) {
             // the launch samples its input level P.step (if >= 1) as well
             const char *tab = P.base + P.r_grid.off;
+            LaunchCfg cfg = P.cfg;
+            cfg.order = tile_order(P.cfg, P.ws_bytes);
             hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
                                    reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF), 1,
-                                   P.tiles.nb, P.tiles.ni, P.cfg,
+                                   P.tiles.nb, P.tiles.ni, cfg,
                                    std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)),
                                    P.id_bits, P.step,
                                    reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
@@ -1073,6 +1080,22 @@ fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t rows, int32_t zchunk)
         plan->cfg.rows = rows;
         plan->cfg.zchunk = zchunk;
     });
+}
+
+fdtd_status fdtd_plan_set_tile_order(fdtd_plan *plan, int32_t order)
+{
+    PLAN_GUARD(plan) {
+        REQUIRE(valid_order(order), FDTD_E_INVALID_ARG, "tile order must be -1 or in [0, 4096]");
+        plan->cfg.order = order;
+    });
+}
+
+fdtd_status fdtd_plan_get_tile_order(const fdtd_plan *plan, int32_t *order, int32_t *used)
+{
+    if (!plan) return FDTD_E_INVALID_ARG;
+    if (order) *order = plan->cfg.order;
+    if (used) *used = tile_order(plan->cfg, plan->ws_bytes);
+    return FDTD_OK;
 }
 
 fdtd_status fdtd_plan_autotune(fdtd_plan *plan, int32_t trial_steps, const char *cache_path,

@@ -2,8 +2,9 @@
 //
 // Every probe is a weighted sum of field samples (the port voltage and
 // current of eq. 4, or one field value).  The sum runs in FP64 in a fixed
-// order: thread t adds terms t, t+B, ... (B = block size, a power of two),
-// then a fixed pairwise tree, so results do not depend on timing.
+// order: thread t adds terms t, t+B, ... (B = block size), the partials
+// above the largest power of two P <= B are folded onto the first B - P,
+// then a fixed pairwise tree over P, so results do not depend on timing.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +26,11 @@ __device__ __forceinline__ double probe_sum(const DevGrid<T> &d, const DevProbes
     }
     red[t] = acc;
     __syncthreads();
-    for (int w = B / 2; w > 0; w >>= 1) {
+    int P = 1;
+    while (2 * P <= B) P *= 2;
+    if (t < B - P) red[t] += red[t + P];
+    __syncthreads();
+    for (int w = P / 2; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }

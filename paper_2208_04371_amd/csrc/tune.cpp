@@ -14,16 +14,18 @@ namespace fdtd {
 
 namespace {
 
-// Candidates: tile rows x z-chunk.
+// Candidates: tile rows x z-chunk x tile order.
 const int TUNE_ROWS[] = {2, 4, 8, 12, 16};
 const int TUNE_Z[] = {4, 8, 16, 32, 64};
+const int TUNE_ORDER[] = {0, 16};
 
 // The cache is a JSON object written one entry per line:
 //   {
-//   "gfx950:...|400x120x80;": [4, 32, 0.0312],
+//   "gfx950:...|400x120x80;": [4, 32, 0.0312, 0],
 //   ...
 //   }
-// (rows, z-chunk, milliseconds per step).  Unknown lines are ignored.
+// (rows, z-chunk, milliseconds per step, tile order; an entry without the
+// order leaves it automatic).  Unknown lines are ignored.
 std::vector<std::pair<std::string, std::string>> cache_read(const char *path)
 {
     std::vector<std::pair<std::string, std::string>> out;
@@ -47,12 +49,13 @@ bool cache_lookup(const char *path, const std::string &key, LaunchCfg &cfg)
 {
     for (const auto &e : cache_read(path)) {
         if (e.first != key) continue;
-        int rows = 0, z = 0;
+        int rows = 0, z = 0, order = -1;
         double ms = 0;
-        if (std::sscanf(e.second.c_str(), "%d , %d , %lf", &rows, &z, &ms) >= 2 && valid_rows(rows) &&
-            z >= 1 && z <= 64) {
+        if (std::sscanf(e.second.c_str(), "%d , %d , %lf , %d", &rows, &z, &ms, &order) >= 2 &&
+            valid_rows(rows) && z >= 1 && z <= 64 && valid_order(order)) {
             cfg.rows = rows;
             cfg.zchunk = z;
+            cfg.order = order;
             return true;
         }
         return false;
@@ -64,7 +67,7 @@ void cache_store(const char *path, const std::string &key, const LaunchCfg &cfg,
 {
     auto entries = cache_read(path);
     char val[128];
-    std::snprintf(val, sizeof val, "%d, %d, %.6g", cfg.rows, cfg.zchunk, ms);
+    std::snprintf(val, sizeof val, "%d, %d, %.6g, %d", cfg.rows, cfg.zchunk, ms, cfg.order);
     bool found = false;
     for (auto &e : entries)
         if (e.first == key) { e.second = val; found = true; }
@@ -134,10 +137,12 @@ hipError_t tune_search(const TuneHooks &h, int32_t trial_steps, const char *cach
     int idx = 0;
     best_index = -1;
     for (int r : TUNE_ROWS)
-        for (int z : TUNE_Z) {
+        for (int z : TUNE_Z)
+        for (int o : TUNE_ORDER) {
             LaunchCfg c;
             c.rows = r;
             c.zchunk = z;
+            c.order = o;
             h.apply(c);
             h.run(1);   // warm-up
             if ((e = hipEventRecord(ev.a, s)) != hipSuccess) return e;

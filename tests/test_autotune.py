@@ -42,7 +42,9 @@ def test_autotune_picks_caches_and_resets(fd, tmp_path):
     assert len(entries) == 1
     (key, val), = entries.items()
     assert key.endswith("96x36x28;96x40x28;96x44x28;")
-    assert val[:2] == [rows, z] and val[2] > 0
+    order = bs.tile_order()[0]
+    assert order in (0, 16)
+    assert val[:2] == [rows, z] and val[2] > 0 and val[3] == order
     # the members were reset: a run now equals a fresh batch in that shape
     bs.run(60)
     ref = fd.BatchSimulation(_probs(), config=(rows, z))
@@ -55,7 +57,7 @@ def test_autotune_picks_caches_and_resets(fd, tmp_path):
     # a second batch of the same shapes takes the cached choice untimed
     again = fd.BatchSimulation(_probs())
     assert again.autotune(trial_steps=3, cache_path=cache) == -1
-    assert again.get_config() == (rows, z)
+    assert again.get_config() == (rows, z) and again.tile_order()[0] == order
     for x in (bs, ref, again):
         x.close()
 
@@ -68,17 +70,20 @@ def test_plan_autotune_picks_caches_and_resets(fd, tmp_path):
     best = sim.autotune(trial_steps=3, cache_path=cache)
     rows, z = sim.get_config()
     print("plan autotune picked", best, rows, z, flush=True)
-    assert 0 <= best < 25
+    assert 0 <= best < 50
     assert rows in (2, 4, 8, 12, 16) and z in (4, 8, 16, 32, 64)
+    order = sim.tile_order()[0]
+    assert order in (0, 16) and best % 2 == (order == 16)
     assert sim.step == 0
     with open(cache) as f:
         entries = json.load(f)
     (key, val), = entries.items()
     assert key.endswith("|96x40x28;")
-    assert val[:2] == [rows, z] and val[2] > 0
+    assert val[:2] == [rows, z] and val[2] > 0 and val[3] == order
     # the plan was reset: a run now equals a fresh plan in that shape
     sim.run()
     ref = fd.Simulation(p, fused=True, config=(rows, z))
+    ref.set_tile_order(order)
     ref.run()
     assert np.array_equal(sim.field(W.EZ), ref.field(W.EZ))
     Va, Ia = sim.spectra()
@@ -87,7 +92,7 @@ def test_plan_autotune_picks_caches_and_resets(fd, tmp_path):
     # a one-member batch of the same shape shares the cache entry
     bs = fd.BatchSimulation([p])
     assert bs.autotune(trial_steps=3, cache_path=cache) == -1
-    assert bs.get_config() == (rows, z)
+    assert bs.get_config() == (rows, z) and bs.tile_order()[0] == order
     # plain kernels have no launch shape to tune
     plain = fd.Simulation(p, fused=False)
     with pytest.raises(fd.FdtdError) as e:

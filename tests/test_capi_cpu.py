@@ -78,6 +78,15 @@ def test_call_order_and_argument_errors(fd):
     with pytest.raises(fd.FdtdError) as e:
         fdtd_plan_autotune(h, 3, stream=0)
     assert e.value.code == -2
+    # tile order: -1 (automatic) by default, [0, 4096] accepted
+    assert fd.fdtd_plan_get_tile_order(h)[0] == -1
+    for bad in (-2, 4097):
+        with pytest.raises(fd.FdtdError) as e:
+            fd.fdtd_plan_set_tile_order(h, bad)
+        assert e.value.code == -1
+    fd.fdtd_plan_set_tile_order(h, 16)
+    assert fd.fdtd_plan_get_tile_order(h) == (16, 16)
+    fd.fdtd_plan_set_tile_order(h, -1)
     # port whose current loop would leave the grid
     h2 = fdtd_plan_create(20, 20, 20, 1, 1, 1, 0.9, units=fd.NORMALIZED)
     with pytest.raises(fd.FdtdError) as e:

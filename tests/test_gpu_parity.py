@@ -163,12 +163,60 @@ def test_small_microstrip_fp32_matches_oracle(fd, small_ref, fused):
 @pytest.mark.parametrize("rows,zchunk", [(2, 64), (2, 5), (4, 1), (4, 32), (8, 7), (12, 9), (16, 3)])
 def test_fused_launch_shapes_agree(fd, rows, zchunk):
     """Every tile height and z-chunk (ragged tails in x, y and z) gives the
-    same fields as the reference launch shape."""
+    same fields and port spectra as the reference launch shape (the probes
+    are sampled by blocks of 64 x R threads: 12 rows is not a power of two)."""
     p = W.small_microstrip(nsteps=150, seed=4)
     ref = fd.Simulation(p, fused=True, config=(4, 32)).run()
     sim = fd.Simulation(p, fused=True, config=(rows, zchunk)).run()
     errs = _field_errors(_fields(sim), _fields(ref))
     assert max(errs) < 1e-6, errs
+    Vs, Is = sim.spectra()
+    Vr, Ir = ref.spectra()
+    assert _rel(Vs[0], Vr[0]) < 1e-6 and _rel(Is[0], Ir[0]) < 1e-6
+
+
+@pytest.mark.parametrize("nx,rows", [(30, 8), (69, 2), (69, 16), (80, 8), (81, 4), (104, 8),
+                                     (128, 12)])
+def test_ragged_x_column_matches_oracle(fd, nx, rows):
+    """Grids whose last x column holds 1..32 cells run it as 16-wide tiles of
+    4R rows (one or two sub-columns; nx = 30 has no 64-wide tile at all,
+    R = 16 gives narrow tiles taller than the grid); 104 = 64 + 40 keeps
+    one partial 64-wide tile and 128 has no ragged column."""
+    p = W.small_microstrip(nx=nx, nsteps=150, pml=6, src_i=8, ports=(10, nx - 10), seed=7)
+    _say(f"ragged x column nx={nx} rows={rows}")
+    o = oracle.Oracle(p).run(p.nsteps)
+    sim = fd.Simulation(p, fused=True, config=(rows, 8)).run()
+    _check_fields(sim, o, 1e-4, norm="l2")
+    Vg, Ig = sim.spectra()
+    Vo, Io = o.spectra()
+    assert _rel(Vg, Vo) < 1e-4 and _rel(Ig, Io) < 1e-4
+
+
+def test_tile_order_changes_timing_only(fd):
+    """Any block-to-tile order gives bit-identical fields and spectra."""
+    p = W.small_microstrip(nsteps=120, seed=3)
+    ref = None
+    for order in (0, 1, 7, 16):
+        sim = fd.Simulation(p, fused=True, config=(4, 4))
+        sim.set_tile_order(order)
+        assert sim.tile_order() == (order, order)
+        sim.run()
+        got = (_fields(sim), sim.spectra())
+        if ref is None:
+            ref = got
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(got[0], ref[0])), order
+            assert all(np.array_equal(a, b) for a, b in zip(got[1], ref[1])), order
+        sim.close()
+    probs = [W.small_microstrip(nsteps=60, ny=36 + 4 * q, seed=q) for q in range(3)]
+    out = []
+    for order in (0, 3):
+        bs = fd.BatchSimulation(probs, config=(8, 4))
+        bs.set_tile_order(order)
+        bs.run(60)
+        out.append([bs.field(q, W.EZ) for q in range(3)])
+        bs.close()
+    assert all(np.array_equal(a, b) for a, b in zip(*out))
 
 
 def test_fused_equals_plain_fp32(fd):
