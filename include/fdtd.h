@@ -272,11 +272,27 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
 /* Launch configuration of the fused kernel: tile rows per block (2, 4, 8,
  * 12 or 16; a block is 64 x rows threads) and the number of z planes one block
  * marches through (1..64).  set returns INVALID_ARG for other values.  The
- * default (at creation) is 8 rows and the longest z-chunk of 16, 8 or 4
- * planes that still yields at least 2048 tiles. */
+ * default (at creation, and after fdtd_batch_set_group_bytes while neither
+ * set_config nor the autotuner has chosen one) is 8 rows and the longest
+ * z-chunk of 16, 8 or 4 planes that still yields at least 2048 tiles in one
+ * launch (of the largest group when the batch is grouped). */
 fdtd_status fdtd_batch_get_config(const fdtd_batch *batch, int32_t *tile_rows,
                                   int32_t *zchunk);
 fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t tile_rows, int32_t zchunk);
+
+/* State budget of the batch schedule.  When the member workspaces add up
+ * to more than `bytes`, the members are split, in their order, into groups
+ * of consecutive members whose workspaces fit it (a larger member forms a
+ * group alone), and fdtd_batch_run advances one group at a time by nsteps:
+ * each group's state then stays in the GPU's memory-side cache for its
+ * whole span instead of streaming from HBM every step.  Otherwise (or with
+ * bytes = 0) all members step in lockstep, one launch pair per step.
+ * Default 256 MiB (the MI355X memory-side cache).  Results do not depend on
+ * the schedule; between fdtd_batch_run calls all members are at the same
+ * step.  Kernel timing counts the launches of each group as steps.  get
+ * returns the number of groups (1 = lockstep). */
+fdtd_status fdtd_batch_set_group_bytes(fdtd_batch *batch, uint64_t bytes);
+fdtd_status fdtd_batch_get_groups(const fdtd_batch *batch, int32_t *ngroups);
 
 /* Order in which the blocks of a fused launch take their tiles.  The GPU
  * deals blocks to its 8 XCDs (each with its own L2) in turn.  0: each XCD
@@ -313,10 +329,17 @@ fdtd_status fdtd_plan_autotune(fdtd_plan *plan, int32_t trial_steps, const char 
 
 /* ---- kernel timing ----------------------------------------------------- */
 
-/* While enabled, every launch of the plan's (or batch's) field-update
- * kernel is bracketed by HIP events on the run stream; the summed device
- * time and launch count are returned by ..._get_kernel_time (which
- * synchronizes the stream).  Enabling clears the totals. */
+/* enable = n >= 1: the steps of each run (the field-update launches of a
+ * plan or batch) are timed by HIP events on the run stream in windows of n
+ * consecutive steps, one event pair per window (a run's last window may be
+ * shorter); ..._get_kernel_time returns the summed window time and the
+ * number of steps it covers (and synchronizes the stream).  n = 1 brackets
+ * each step alone.  A window's time includes the gaps between its launches
+ * and any probe or DFT launch between its steps.  0 disables; a negative
+ * value is INVALID_ARG.  Setting clears the totals.  An event pair costs
+ * the host about as much as a 400x120x80 step takes on the GPU and adds its
+ * own latency on the GPU, so n = 1 slows such short steps; windows of 16
+ * steps keep that cost out of the measurement. */
 fdtd_status fdtd_plan_set_timing(fdtd_plan *plan, int32_t enable);
 fdtd_status fdtd_plan_get_kernel_time(fdtd_plan *plan, double *ms, int64_t *launches);
 fdtd_status fdtd_batch_set_timing(fdtd_batch *batch, int32_t enable);

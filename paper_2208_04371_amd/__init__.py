@@ -189,8 +189,9 @@ def fdtd_plan_autotune(plan, trial_steps: int = 20, cache_path: Optional[str] = 
     return best.value
 
 
-def fdtd_plan_set_timing(plan, enable: bool):
-    check(lib().fdtd_plan_set_timing(plan, 1 if enable else 0), "fdtd_plan_set_timing", plan)
+def fdtd_plan_set_timing(plan, enable):
+    """enable: False/0 off, True/1 every step, n > 1 every n-th step."""
+    check(lib().fdtd_plan_set_timing(plan, int(enable)), "fdtd_plan_set_timing", plan)
 
 
 def fdtd_plan_get_kernel_time(plan):
@@ -402,6 +403,16 @@ class BatchSimulation:
         check(lib().fdtd_batch_set_tile_order(self.handle, order), "fdtd_batch_set_tile_order",
               self.handle, batch=True)
 
+    def set_group_bytes(self, nbytes: int):
+        check(lib().fdtd_batch_set_group_bytes(self.handle, nbytes), "fdtd_batch_set_group_bytes",
+              self.handle, batch=True)
+
+    def groups(self) -> int:
+        n = C.c_int32()
+        check(lib().fdtd_batch_get_groups(self.handle, C.byref(n)), "fdtd_batch_get_groups",
+              self.handle, batch=True)
+        return n.value
+
     def tile_order(self):
         o, u = C.c_int32(), C.c_int32()
         check(lib().fdtd_batch_get_tile_order(self.handle, C.byref(o), C.byref(u)),
@@ -422,8 +433,8 @@ class BatchSimulation:
               batch=True)
         return best.value
 
-    def set_timing(self, enable: bool):
-        check(lib().fdtd_batch_set_timing(self.handle, 1 if enable else 0),
+    def set_timing(self, enable):
+        check(lib().fdtd_batch_set_timing(self.handle, int(enable)),
               "fdtd_batch_set_timing", self.handle, batch=True)
 
     def kernel_time(self):

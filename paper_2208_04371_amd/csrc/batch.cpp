@@ -66,9 +66,9 @@ fdtd_status bguard(Batch *b, F &&f)
 }
 
 // Device tables of a bound batch (offsets inside its workspace):
-// [grids parity 0][grids parity 1][tile sets][probes][dft]
+// [grids parity 0][grids parity 1][tile sets][group tile sets][probes][dft]
 struct Tables {
-    size_t grids[2], sets, probes, dft, bytes;
+    size_t grids[2], sets, gsets, probes, dft, bytes;
 };
 
 Tables table_layout(int n)
@@ -78,6 +78,7 @@ Tables table_layout(int n)
     t.grids[0] = cur; cur = al256(cur + sizeof(DevGrid<float>) * n);
     t.grids[1] = cur; cur = al256(cur + sizeof(DevGrid<float>) * n);
     t.sets = cur; cur = al256(cur + sizeof(TileSet) * n);
+    t.gsets = cur; cur = al256(cur + sizeof(TileSet) * n);
     t.probes = cur; cur = al256(cur + sizeof(DevProbes) * n);
     t.dft = cur; cur = al256(cur + sizeof(DevDft) * n);
     t.bytes = cur;
@@ -98,12 +99,45 @@ void compute_blocks(Batch &B)
     }
     B.nb_total = nb;
     B.ni_total = ni;
+    // groups: consecutive members packed greedily under group_bytes
+    B.groups.clear();
+    B.gsets = B.sets;
+    size_t total = 0;
+    for (const Plan *P : B.plans) total += P->ws_bytes;
+    for (size_t q = 0; q < B.plans.size(); ++q) {
+        const size_t w = B.plans[q]->ws_bytes;
+        const bool fresh = B.groups.empty() ||
+                           (B.group_bytes > 0 && total > B.group_bytes &&
+                            B.groups.back().bytes + w > B.group_bytes);
+        if (fresh) B.groups.push_back({(int32_t)q, 0, 0, 0, 0});
+        Batch::Group &g = B.groups.back();
+        TileSet &t = B.gsets[q];
+        t.sb = g.nb;
+        t.si = g.ni;
+        g.count += 1;
+        g.nb += t.nb;
+        g.ni += t.ni;
+        g.bytes += w;
+    }
     B.lut_cap = 1;
     B.id_bits = 5;
     for (const Plan *P : B.plans) {
         B.lut_cap = std::max<int32_t>(B.lut_cap, (int32_t)(P->lut[0].size() / 4));
         if (P->id_bits != 5) B.id_bits = 8;
     }
+}
+
+// Default launch shape, sized for the largest group (the launches of a
+// grouped schedule cover one group each).
+void default_config(Batch &B)
+{
+    size_t big = 0;
+    for (size_t q = 1; q < B.groups.size(); ++q)
+        if (B.groups[q].bytes > B.groups[big].bytes) big = q;
+    const LaunchCfg keep = B.cfg;
+    B.cfg = default_launch(B.plans.data() + B.groups[big].first, (size_t)B.groups[big].count);
+    B.cfg.order = keep.order;
+    compute_blocks(B);
 }
 
 // Upload the instance tables for the current parity of the member plans.
@@ -130,60 +164,83 @@ void upload_tables(Batch &B, hipStream_t s)
     hcheck(hipMemcpyAsync(base + t.grids[0], g0.data(), sizeof(DevGrid<float>) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.grids[1], g1.data(), sizeof(DevGrid<float>) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.sets, B.sets.data(), sizeof(TileSet) * n, hipMemcpyHostToDevice, s), "table");
+    hcheck(hipMemcpyAsync(base + t.gsets, B.gsets.data(), sizeof(TileSet) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.probes, pr.data(), sizeof(DevProbes) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipMemcpyAsync(base + t.dft, df.data(), sizeof(DevDft) * n, hipMemcpyHostToDevice, s), "table");
     hcheck(hipStreamSynchronize(s), "table sync");
 }
 
-// Fold the pending history samples of every member into its DFTs (all
-// members step, sample and fold in lockstep).
-void batch_flush(Batch &B, hipStream_t s)
+// Fold the pending history samples of members [a, a + m) into their DFTs
+// (the members of one span step, sample and fold in lockstep).
+void span_flush(Batch &B, int a, int m, hipStream_t s)
 {
-    Plan &P0 = *B.plans[0];
+    Plan &P0 = *B.plans[a];
     if (P0.sampled > P0.dft_n) {
         const Tables t = table_layout((int)B.plans.size());
-        hcheck(launch_dft_batch(reinterpret_cast<const DevDft *>(B.base + B.r_table.off + t.dft),
-                                (int)B.plans.size(), B.max_probes, B.max_nf, P0.dft_n + 1,
-                                P0.sampled - P0.dft_n, s), "batch dft");
-        for (Plan *P : B.plans) P->dft_n = P0.sampled;
+        hcheck(launch_dft_batch(reinterpret_cast<const DevDft *>(B.base + B.r_table.off + t.dft) + a,
+                                m, B.max_probes, B.max_nf, P0.dft_n + 1, P0.sampled - P0.dft_n, s),
+               "batch dft");
+        for (int q = a; q < a + m; ++q) B.plans[q]->dft_n = P0.sampled;
     }
 }
 
+// Advance members [a, a + m) by nsteps steps in lockstep, one fused launch
+// pair per step.  sets_dev holds their tile sets with first blocks counted
+// from member a; nb, ni are their tile totals; state is their workspace.
+void run_span(Batch &B, int a, int m, const TileSet *sets_dev, int32_t nb, int32_t ni,
+              size_t state, int64_t nsteps, hipStream_t s)
+{
+    const Tables t = table_layout((int)B.plans.size());
+    char *tb = B.base + B.r_table.off;
+    const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes) + a;
+    Plan &P0 = *B.plans[a];
+    const bool sample = B.max_probes > 0;
+    LaunchCfg cfg = B.cfg;
+    cfg.order = tile_order(B.cfg, state);
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]) + a;
+        hipEvent_t e0, e1;
+        hcheck(B.timer.step(e0, e1, q == 0, q + 1 == nsteps), "timer");
+        // every member's step, plus sampling of its input level
+        hcheck(launch_fused(g, sets_dev, m, nb, ni, cfg, B.lut_cap, B.id_bits, P0.step, probes,
+                            B.max_probes, sample, s, e0, e1),
+               "batch step");
+        const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
+        for (int r = a; r < a + m; ++r) {
+            Plan *P = B.plans[r];
+            P->parity = 1 - P->parity;
+            P->step += 1;
+            P->sampled = sampled;
+        }
+        if (P0.sampled - P0.dft_n >= P0.K - 1) span_flush(B, a, m, s);
+    }
+    if (sample && P0.sampled < P0.step) {
+        const DevGrid<float> *gc = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]) + a;
+        hcheck(launch_probe_batch(gc, probes, m, B.max_probes, P0.step, s), "batch probe");
+        for (int r = a; r < a + m; ++r) B.plans[r]->sampled = P0.step;
+    }
+    span_flush(B, a, m, s);
+}
+
+// All members advance by nsteps.  With one group, in lockstep; with
+// several, group after group (each group's state stays in the memory-side
+// cache for its whole span).  Members are independent, so both give the
+// same results.
 void batch_run(Batch &B, int64_t nsteps, hipStream_t s)
 {
     BREQUIRE(B.bound, FDTD_E_STATE, "batch not bound");
     BREQUIRE(nsteps >= 0, FDTD_E_INVALID_ARG, "negative step count");
     const int n = (int)B.plans.size();
     const Tables t = table_layout(n);
-    char *tb = B.base + B.r_table.off;
-    const TileSet *sets = reinterpret_cast<const TileSet *>(tb + t.sets);
-    const DevProbes *probes = reinterpret_cast<const DevProbes *>(tb + t.probes);
-    Plan &P0 = *B.plans[0];
-    const bool sample = B.max_probes > 0;
-    LaunchCfg cfg = B.cfg;
-    cfg.order = tile_order(B.cfg, B.ws_bytes);
-    for (int64_t q = 0; q < nsteps; ++q) {
-        const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
-        hipEvent_t e0, e1;
-        hcheck(B.timer.slot(e0, e1), "timer");
-        // every instance's step, plus sampling of its input level
-        hcheck(launch_fused(g, sets, n, B.nb_total, B.ni_total, cfg, B.lut_cap, B.id_bits, P0.step, probes,
-                            B.max_probes, sample, s, e0, e1),
-               "batch step");
-        const int64_t sampled = (sample && P0.step >= 1) ? std::max(P0.sampled, P0.step) : P0.sampled;
-        for (Plan *P : B.plans) {
-            P->parity = 1 - P->parity;
-            P->step += 1;
-            P->sampled = sampled;
-        }
-        if (P0.sampled - P0.dft_n >= P0.K - 1) batch_flush(B, s);
+    const char *tb = B.base + B.r_table.off;
+    if (B.groups.size() <= 1) {
+        run_span(B, 0, n, reinterpret_cast<const TileSet *>(tb + t.sets), B.nb_total, B.ni_total,
+                 B.ws_bytes, nsteps, s);
+        return;
     }
-    if (sample && P0.sampled < P0.step) {
-        const DevGrid<float> *gc = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]);
-        hcheck(launch_probe_batch(gc, probes, n, B.max_probes, P0.step, s), "batch probe");
-        for (Plan *P : B.plans) P->sampled = P0.step;
-    }
-    batch_flush(B, s);
+    for (const Batch::Group &g : B.groups)
+        run_span(B, g.first, g.count, reinterpret_cast<const TileSet *>(tb + t.gsets) + g.first, g.nb,
+                 g.ni, g.bytes, nsteps, s);
 }
 
 }  // namespace
@@ -232,8 +289,8 @@ fdtd_status fdtd_batch_create(fdtd_plan *const *plans, int32_t n, fdtd_batch **o
                     P->finalized = false;
                     plan_finalize(*P);
                 }
-        b->cfg = default_launch(b->plans.data(), b->plans.size());
         compute_blocks(*b);
+        default_config(*b);
     });
     if (st != FDTD_OK) {
         create_error() = b->err;
@@ -314,9 +371,28 @@ fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t rows, int32_t zchun
         BREQUIRE(zchunk >= 1 && zchunk <= 64, FDTD_E_INVALID_ARG, "z-chunk must be in [1, 64]");
         batch->cfg.rows = rows;
         batch->cfg.zchunk = zchunk;
+        batch->cfg_auto = false;
         compute_blocks(*batch);
         if (batch->bound) upload_tables(*batch, nullptr);
     });
+}
+
+fdtd_status fdtd_batch_set_group_bytes(fdtd_batch *batch, uint64_t bytes)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        batch->group_bytes = (size_t)bytes;
+        compute_blocks(*batch);
+        if (batch->cfg_auto) default_config(*batch);
+        if (batch->bound) upload_tables(*batch, nullptr);
+    });
+}
+
+fdtd_status fdtd_batch_get_groups(const fdtd_batch *batch, int32_t *ngroups)
+{
+    if (!batch || !ngroups) return FDTD_E_INVALID_ARG;
+    *ngroups = (int32_t)batch->groups.size();
+    return FDTD_OK;
 }
 
 fdtd_status fdtd_batch_set_tile_order(fdtd_batch *batch, int32_t order)
@@ -345,7 +421,9 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
         BREQUIRE(B.bound, FDTD_E_STATE, "batch not bound");
         BREQUIRE(trial_steps >= 1, FDTD_E_INVALID_ARG, "trial_steps must be >= 1");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const std::string key = tune_device_name() + "|" + tune_shape_key(B.plans.data(), B.plans.size());
+        // the grouped schedule launches per group: its best shape differs
+        std::string key = tune_device_name() + "|" + tune_shape_key(B.plans.data(), B.plans.size());
+        if (B.groups.size() > 1) key += "groups=" + std::to_string(B.groups.size()) + ";";
         TimerPause pause(B.timer);   // trial launches are not the caller's
         TuneHooks h;
         h.apply = [&](const LaunchCfg &c) {
@@ -356,6 +434,7 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
         LaunchCfg best = B.cfg;
         int32_t best_i = -1;
         hcheck(tune_search(h, trial_steps, cache_path, key, s, best, best_i), "autotune");
+        B.cfg_auto = false;
         if (best_i >= 0) {
             for (Plan *P : B.plans) plan_reset(*P, s);
             hcheck(hipStreamSynchronize(s), "sync");
@@ -368,9 +447,11 @@ fdtd_status fdtd_batch_set_timing(fdtd_batch *batch, int32_t enable)
 {
     if (!batch) return FDTD_E_INVALID_ARG;
     return bguard(batch, [&]() {
+        BREQUIRE(enable >= 0, FDTD_E_INVALID_ARG, "negative timing stride");
         hcheck(batch->timer.drain(), "timer drain");
         batch->timer.reset();
         batch->timer.on = enable != 0;
+        batch->timer.every = enable > 1 ? enable : 1;
     });
 }
 

@@ -129,18 +129,25 @@ struct Region {
     size_t off = 0, bytes = 0;
 };
 
-// Pool of HIP event pairs that bracket field-update launches.  A pair is
-// read back only when it is about to be reused (or on drain), so timing
-// never stalls the launch queue.
+// Pool of HIP event pairs that time the steps of a run in windows of
+// `every` consecutive steps (one pair per window; a run's last window may
+// be shorter).  A pair is read back only when it is about to be reused (or
+// on drain), so timing never stalls the launch queue.
 struct KernelTimer {
     static constexpr size_t SLOTS = 512;
     bool on = false;
+    int32_t every = 1;            // steps per window
     double ms = 0;
-    int64_t launches = 0;
+    int64_t launches = 0;         // steps of the windows read back
     std::vector<hipEvent_t> ev;   // 2 per slot
-    std::vector<char> used;
+    std::vector<int64_t> used;    // steps of the slot's closed window, 0 = free
     size_t next = 0;
-    hipError_t slot(hipEvent_t &a, hipEvent_t &b);
+    long open = -1;               // slot of the open window
+    int32_t in_window = 0;        // steps in the open window
+    // Events to record around the next step: a opens a window, b closes it
+    // (full, or `last` step of the run); either may be null.  A window left
+    // open by a run that failed is dropped at the `first` step of the next.
+    hipError_t step(hipEvent_t &a, hipEvent_t &b, bool first, bool last);
     hipError_t drain();
     void reset();
     void destroy();
@@ -228,6 +235,13 @@ struct Batch {
     bool bound = false;
     std::vector<TileSet> sets;          // per plan: tile decomposition and first blocks
     int32_t nb_total = 0, ni_total = 0; // boundary / interior tiles of all plans
+    // Groups of consecutive members whose state fits group_bytes (0: one
+    // group of all); with several, a run advances one group at a time.
+    size_t group_bytes = MALL_BYTES;
+    bool cfg_auto = true;               // launch shape not set by the caller
+    struct Group { int32_t first, count, nb, ni; size_t bytes; };
+    std::vector<Group> groups;
+    std::vector<TileSet> gsets;         // as sets, first blocks counted per group
     int32_t lut_cap = 1;                // largest coefficient table of the plans
     int32_t id_bits = 8;                // 5 if every plan packs its ids in 16 bits
     int32_t max_probes = 0;

@@ -598,31 +598,41 @@ static void flush_dft(Plan &P, hipStream_t s)
 
 }  // namespace fdtd
 
-hipError_t fdtd::KernelTimer::slot(hipEvent_t &a, hipEvent_t &b)
+hipError_t fdtd::KernelTimer::step(hipEvent_t &a, hipEvent_t &b, bool first, bool last)
 {
     a = b = nullptr;
     if (!on) return hipSuccess;
-    if (ev.empty()) {
-        ev.assign(2 * SLOTS, nullptr);
-        used.assign(SLOTS, 0);
-        for (auto &e : ev) {
-            const hipError_t r = hipEventCreate(&e);
-            if (r != hipSuccess) return r;
+    if (first) open = -1;
+    if (open < 0) {
+        if (ev.empty()) {
+            ev.assign(2 * SLOTS, nullptr);
+            used.assign(SLOTS, 0);
+            for (auto &e : ev) {
+                const hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+            }
         }
+        if (used[next]) {
+            hipError_t r = hipEventSynchronize(ev[2 * next + 1]);
+            if (r != hipSuccess) return r;
+            float t = 0;
+            r = hipEventElapsedTime(&t, ev[2 * next], ev[2 * next + 1]);
+            if (r != hipSuccess) return r;
+            ms += t;
+            launches += used[next];
+            used[next] = 0;
+        }
+        open = (long)next;
+        next = (next + 1) % SLOTS;
+        in_window = 0;
+        a = ev[2 * open];
     }
-    if (used[next]) {
-        hipError_t r = hipEventSynchronize(ev[2 * next + 1]);
-        if (r != hipSuccess) return r;
-        float t = 0;
-        r = hipEventElapsedTime(&t, ev[2 * next], ev[2 * next + 1]);
-        if (r != hipSuccess) return r;
-        ms += t;
-        launches += 1;
+    in_window += 1;
+    if (in_window >= every || last) {
+        b = ev[2 * open + 1];
+        used[open] = in_window;
+        open = -1;
     }
-    used[next] = 1;
-    a = ev[2 * next];
-    b = ev[2 * next + 1];
-    next = (next + 1) % SLOTS;
     return hipSuccess;
 }
 
@@ -636,7 +646,7 @@ hipError_t fdtd::KernelTimer::drain()
         r = hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]);
         if (r != hipSuccess) return r;
         ms += t;
-        launches += 1;
+        launches += used[q];
         used[q] = 0;
     }
     return hipSuccess;
@@ -647,6 +657,8 @@ void fdtd::KernelTimer::reset()
     for (auto &u : used) u = 0;
     ms = 0;
     launches = 0;
+    open = -1;
+    in_window = 0;
 }
 
 void fdtd::KernelTimer::destroy()
@@ -674,7 +686,7 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
     }
     for (int64_t t = 0; t < nsteps; ++t) {
         hipEvent_t e0, e1;
-        hip_check(P.timer.slot(e0, e1), "timer");
+        hip_check(P.timer.step(e0, e1, t == 0, t + 1 == nsteps), "timer");
         if (fused) {
             // the launch samples its input level P.step (if >= 1) as well
             const char *tab = P.base + P.r_grid.off;
@@ -1129,9 +1141,11 @@ fdtd_status fdtd_plan_autotune(fdtd_plan *plan, int32_t trial_steps, const char 
 fdtd_status fdtd_plan_set_timing(fdtd_plan *plan, int32_t enable)
 {
     PLAN_GUARD(plan) {
+        REQUIRE(enable >= 0, FDTD_E_INVALID_ARG, "negative timing stride");
         hip_check(plan->timer.drain(), "timer drain");
         plan->timer.reset();
         plan->timer.on = enable != 0;
+        plan->timer.every = enable > 1 ? enable : 1;
     });
 }
 

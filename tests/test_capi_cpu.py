@@ -87,6 +87,13 @@ def test_call_order_and_argument_errors(fd):
     fd.fdtd_plan_set_tile_order(h, 16)
     assert fd.fdtd_plan_get_tile_order(h) == (16, 16)
     fd.fdtd_plan_set_tile_order(h, -1)
+    # timing stride: 0 off, n >= 1 every n-th step, negative refused
+    with pytest.raises(fd.FdtdError) as e:
+        fd.fdtd_plan_set_timing(h, -1)
+    assert e.value.code == -1
+    fd.fdtd_plan_set_timing(h, 16)
+    assert fd.fdtd_plan_get_kernel_time(h) == (0.0, 0)
+    fd.fdtd_plan_set_timing(h, 0)
     # port whose current loop would leave the grid
     h2 = fdtd_plan_create(20, 20, 20, 1, 1, 1, 0.9, units=fd.NORMALIZED)
     with pytest.raises(fd.FdtdError) as e:

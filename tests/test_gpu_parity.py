@@ -219,6 +219,22 @@ def test_tile_order_changes_timing_only(fd):
     assert all(np.array_equal(a, b) for a, b in zip(*out))
 
 
+def test_kernel_timer_windows_cover_every_step(fd):
+    p = W.small_microstrip(nsteps=40)
+    sim = fd.Simulation(p, fused=True)
+    for every in (1, 4, 16, 64):
+        fd.fdtd_plan_set_timing(sim.handle, every)
+        sim.reset()
+        sim.run(23)                  # windows end with each run
+        sim.run(17)
+        ms, n = fd.fdtd_plan_get_kernel_time(sim.handle)
+        assert n == 40 and ms > 0, (every, n, ms)
+    fd.fdtd_plan_set_timing(sim.handle, 0)
+    sim.run(5)
+    assert fd.fdtd_plan_get_kernel_time(sim.handle) == (0.0, 0)
+    sim.close()
+
+
 def test_fused_equals_plain_fp32(fd):
     p = W.small_microstrip(nsteps=300, seed=2, sigma_strip=5.8e7)
     a = fd.Simulation(p, fused=True).run()
@@ -326,6 +342,30 @@ def _many_materials(nmat=4, seed=21, block=(8, 8, 16)):
     sub = p.cells < 2   # keep the strip
     p.cells[sub] = (base + full[sub]).astype(np.uint8)
     return p
+
+
+@pytest.mark.parametrize("budget", [0, 1, 20 << 20])
+def test_batch_group_schedules_agree(fd, budget):
+    """A batch run group by group (each member alone: budget 1; groups of a
+    few members: 20 MiB) gives the same bits as lockstep and as the single
+    runs, across a mid-run DFT fold (600 steps) and a split run."""
+    probs = [W.small_microstrip(nsteps=600, ny=36 + 4 * q, seed=q) for q in range(4)]
+    probs.append(W.pec_cavity(n=20, nsteps=600, fp32=True))
+    bs = fd.BatchSimulation(probs)
+    bs.set_group_bytes(budget)
+    ng = bs.groups()
+    _say(f"batch group budget {budget}: {ng} groups")
+    assert ng == {0: 1, 1: len(probs), 20 << 20: 3}[budget]
+    bs.run(250)
+    bs.run(350)
+    for q, p in enumerate(probs):
+        s = fd.Simulation(p, fused=True, config=bs.get_config()).run(600)
+        Vb, Ib = bs.spectra(q)
+        Vs, Is = s.spectra()
+        assert np.array_equal(Vb, Vs) and np.array_equal(Ib, Is), f"instance {q} spectra"
+        assert np.array_equal(bs.field(q, W.EZ), s.field(W.EZ)), f"instance {q} Ez"
+        s.close()
+    bs.close()
 
 
 def test_batch_mixed_id_widths(fd):
