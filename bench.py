@@ -258,8 +258,11 @@ def main():
                          "hbm_frac": round(vb / (kavg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         probs = W.batched_smatrix(nsteps=2000)
         bs = fd.BatchSimulation(probs)
-        bs.run(20)
-        bs.reset()
+        # launch shape from the autotuner (searched outside the timed region;
+        # it resets the members)
+        bpick = bs.autotune(trial_steps=4)
+        brows, bz = bs.get_config()
+        border = bs.tile_order()
         bs.set_timing(TIMING_EVERY)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -278,9 +281,38 @@ def main():
         var["batched_fp32_12x"] = {
             "value": round(cells_b * 2000 / dt / 1e6, 1), "unit": "Mcell-updates/s",
             "timesteps": 2000, "instances": len(probs), "cells": cells_b, "groups": groups,
+            "autotuned": {"candidate": bpick, "tile_rows": brows, "zchunk": bz,
+                          "tile_order": border[1]},
             "avg_step_us": round(step_ms * 1e3, 2),
             "hbm_frac": round(bytes_b / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bs.close()
+        # the 16-instance geometry sweep of uneven shapes with its launch
+        # shape chosen by the autotuner (no cache file: searched here, and
+        # the search is outside the timed region)
+        sp = W.geometry_sweep(nsteps=600)
+        ss = fd.BatchSimulation(sp)
+        pick = ss.autotune(trial_steps=4)
+        srows, sz = ss.get_config()
+        sorder = ss.tile_order()
+        ss.set_timing(TIMING_EVERY)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ss.run(600)
+        for q in range(len(sp)):
+            ss.spectra(q)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sms, _ = ss.kernel_time()
+        cells_s = sum(p.ncells for p in sp)
+        bytes_s = sum(algorithmic_bytes(p)[0] for p in sp)
+        var["sweep_16x_autotuned"] = {
+            "value": round(cells_s * 600 / dt / 1e6, 1), "unit": "Mcell-updates/s",
+            "timesteps": 600, "instances": len(sp), "cells": cells_s, "groups": ss.groups(),
+            "autotuned": {"candidate": pick, "tile_rows": srows, "zchunk": sz,
+                          "tile_order": sorder[1]},
+            "avg_step_us": round(sms / 600 * 1e3, 2),
+            "hbm_frac": round(bytes_s / (sms / 600 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        ss.close()
         # the 1024x512x256 layered lossy line: the grid far larger than the
         # caches, in its default launch shape
         lp = W.large_line(nsteps=300)
