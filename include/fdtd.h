@@ -292,6 +292,10 @@ fdtd_status fdtd_batch_set_config(fdtd_batch *batch, int32_t tile_rows, int32_t 
  * step.  Kernel timing counts the launches of each group as steps.  get
  * returns the number of groups (1 = lockstep). */
 fdtd_status fdtd_batch_set_group_bytes(fdtd_batch *batch, uint64_t bytes);
+/* (set_group_bytes, set_config and set_tile_order on a bound batch rewrite
+ * its launch tables through the null stream and wait for the copy: call them
+ * between runs, not while a run of the batch may still execute on another
+ * stream.) */
 fdtd_status fdtd_batch_get_groups(const fdtd_batch *batch, int32_t *ngroups);
 
 /* Order in which the blocks of a fused launch take their tiles.  The GPU
