@@ -265,7 +265,7 @@ def main():
         bs = fd.BatchSimulation(probs)
         # launch shape from the autotuner (searched outside the timed region;
         # it resets the members)
-        bpick = bs.autotune(trial_steps=4)
+        bpick = bs.autotune(trial_steps=16)
         brows, bz = bs.get_config()
         border = bs.tile_order()
         bs.set_timing(TIMING_EVERY)
@@ -287,7 +287,7 @@ def main():
             "value": round(cells_b * 2000 / dt / 1e6, 1), "unit": "Mcell-updates/s",
             "timesteps": 2000, "instances": len(probs), "cells": cells_b, "groups": groups,
             "autotuned": {"candidate": bpick, "tile_rows": brows, "zchunk": bz,
-                          "tile_order": border[1]},
+                          "tile_order": "automatic" if border[0] < 0 else border[0]},
             "avg_step_us": round(step_ms * 1e3, 2),
             "hbm_frac": round(bytes_b / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bs.close()
@@ -296,7 +296,7 @@ def main():
         # the search is outside the timed region)
         sp = W.geometry_sweep(nsteps=600)
         ss = fd.BatchSimulation(sp)
-        pick = ss.autotune(trial_steps=4)
+        pick = ss.autotune(trial_steps=16)
         srows, sz = ss.get_config()
         sorder = ss.tile_order()
         ss.set_timing(TIMING_EVERY)
@@ -314,7 +314,7 @@ def main():
             "value": round(cells_s * 600 / dt / 1e6, 1), "unit": "Mcell-updates/s",
             "timesteps": 600, "instances": len(sp), "cells": cells_s, "groups": ss.groups(),
             "autotuned": {"candidate": pick, "tile_rows": srows, "zchunk": sz,
-                          "tile_order": sorder[1]},
+                          "tile_order": "automatic" if sorder[0] < 0 else sorder[0]},
             "avg_step_us": round(sms / 600 * 1e3, 2),
             "hbm_frac": round(bytes_s / (sms / 600 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         ss.close()

@@ -256,7 +256,7 @@ fdtd_status fdtd_batch_reset(fdtd_batch *batch, void *stream);
 fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 
 /* Choose the tile height (2, 4, 8, 12, 16 rows), z-chunk (4, 8, 16, 32, 64
- * planes) and tile order (0 or 16, see fdtd_batch_set_tile_order) of the
+ * planes) and tile order (automatic or 16, see fdtd_batch_set_tile_order) of the
  * batched kernel by timing each candidate
  * for `trial_steps` steps; the member states are reset afterwards.
  * cache_path (may be NULL) names a JSON file keyed by GPU architecture and

@@ -14,10 +14,11 @@ namespace fdtd {
 
 namespace {
 
-// Candidates: tile rows x z-chunk x tile order.
+// Candidates: tile rows x z-chunk x tile order (automatic, which follows
+// each launch's state size, or runs of 16).
 const int TUNE_ROWS[] = {2, 4, 8, 12, 16};
 const int TUNE_Z[] = {4, 8, 16, 32, 64};
-const int TUNE_ORDER[] = {0, 16};
+const int TUNE_ORDER[] = {-1, 16};
 
 // The cache is a JSON object written one entry per line:
 //   {
