@@ -26,9 +26,10 @@
  * Parity notes: the discrete energy invariant, the exact single-mode Yee
  * evolution, cavity resonances, the parallel-plate impedance and the source
  * spectrum pin this file (see the oracle tests).  The edge averaging of the
- * permittivity at material interfaces and the absorbing-layer defaults are
- * readings the paper leaves open; they are pinned only partly (uniform and
- * layered media) and otherwise parity unpinned.
+ * permittivity at material interfaces, a reading the paper leaves open, is
+ * pinned by modes in 1-cell alternating layers.  The absorbing-layer
+ * defaults, another such reading, are pinned only through the absorption
+ * of each axis, not value by value: parity unpinned there.
  */
 #include <math.h>
 #include <stdint.h>

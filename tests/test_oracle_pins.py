@@ -150,6 +150,62 @@ def test_single_eigenmode_follows_yee_dispersion(m, n):
     assert err < 1e-12, err
 
 
+@pytest.mark.parametrize("comp,layers", [("z", "x"), ("z", "y"), ("x", "y"), ("x", "z")])
+def test_interface_averaging_in_one_cell_layers(comp, layers):
+    """Edge permittivity is the mean over the cells that share the edge (the
+    reading taken for material interfaces).  With 1-cell layers of eps 2 and
+    5 alternating along an axis across the edges, every edge of the mode's
+    component is shared by two cells of each, so a standing mode uniform
+    along that component (TM_mn0 for Ez, its rotation for Ex) evolves
+    exactly as in a uniform eps 3.5, at the exact Yee frequency.  A harmonic
+    mean, or a mean over the wrong cells, changes the frequency."""
+    N = 24
+    eps = (2.0, 5.0)
+    p = W.pec_cavity(n=N, source=False)
+    p.materials = [W.Material(eps[0]), W.Material(eps[1])]
+    kk, jj, ii = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    p.cells = ({"x": ii, "y": jj, "z": kk}[layers] % 2).astype(np.uint8)
+    o = oracle.Oracle(p)
+    dt = o.dt
+    a, b = 2 * math.pi / N, math.pi / N
+    s2 = math.sin(a / 2) ** 2 + math.sin(b / 2) ** 2
+
+    def omega(e):
+        return 2 * math.asin(dt * math.sqrt(s2 / e)) / dt
+
+    kk, jj, ii = np.meshgrid(np.arange(N + 1), np.arange(N + 1), np.arange(N + 1), indexing="ij")
+    if comp == "z":
+        # Ez = sin(a i) sin(b j); H^{-1/2} = (dt/2) curl E^0
+        E = np.sin(a * ii) * np.sin(b * jj)
+        E[N, :, :] = 0.0
+        H1 = 0.5 * dt * np.sin(a * ii) * 2 * np.cos(b * (jj + 0.5)) * math.sin(b / 2)
+        H2 = -0.5 * dt * np.sin(b * jj) * 2 * np.cos(a * (ii + 0.5)) * math.sin(a / 2)
+        H1[:, N, :] = 0; H1[N, :, :] = 0
+        H2[:, :, N] = 0; H2[N, :, :] = 0
+        ce, c1, c2 = W.EZ, W.HX, W.HY
+    else:
+        # Ex = sin(a j) sin(b k): Hy = (dt/2) dEx/dz, Hz = -(dt/2) dEx/dy
+        E = np.sin(a * jj) * np.sin(b * kk)
+        E[:, :, N] = 0.0
+        H1 = 0.5 * dt * np.sin(a * jj) * 2 * np.cos(b * (kk + 0.5)) * math.sin(b / 2)
+        H2 = -0.5 * dt * np.sin(b * kk) * 2 * np.cos(a * (jj + 0.5)) * math.sin(a / 2)
+        H1[:, :, N] = 0; H1[N, :, :] = 0
+        H2[:, :, N] = 0; H2[:, N, :] = 0
+        ce, c1, c2 = W.EX, W.HY, W.HZ
+    o.set_field(ce, E)
+    o.set_field(c1, H1)
+    o.set_field(c2, H2)
+    steps = 600
+    o.run(steps)
+    got = o.field(ce)
+    expect = math.cos(omega(0.5 * (eps[0] + eps[1])) * steps * dt) * E
+    err = np.max(np.abs(got - expect)) / np.max(np.abs(E))
+    assert err < 1e-11, err
+    # the harmonic mean would be far off
+    wrong = math.cos(omega(2 / (1 / eps[0] + 1 / eps[1])) * steps * dt) * E
+    assert np.max(np.abs(got - wrong)) / np.max(np.abs(E)) > 1e-2
+
+
 def test_cavity_resonances():
     """The probe spectrum of the soft-driven PEC cube peaks at the Yee
     frequencies of the modes the centre source excites (odd m, n)."""
