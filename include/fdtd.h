@@ -308,6 +308,21 @@ fdtd_status fdtd_batch_get_groups(const fdtd_batch *batch, int32_t *ngroups);
  * order changes timing only, never results.  get returns the setting and
  * the order launches use (*used, from the workspace size once known). */
 fdtd_status fdtd_batch_set_tile_order(fdtd_batch *batch, int32_t order);
+
+/* Streaming (non-temporal) stores of the fields a fused launch writes.  The
+ * outputs of a step are read again only by the next step: once the state
+ * exceeds the 256 MB memory-side cache, caching them evicts the inputs still
+ * to be read (1024x512x256: 1484 against 1538 us per step), while for a
+ * state inside that cache they would push next step's inputs out of it
+ * (400x120x80: 77 against 56 us).  Not far above the cache size much of
+ * the state still hits it and the outcome depends on the grid (a 296 MiB
+ * microstrip gains 5 %, sweep grids of 289 and 308 MiB lose heavily).
+ * mode: 1 on, 0 off, -1 (default) automatic, on for a launch whose
+ * workspace (a batch: its group's) exceeds 512 MiB.  Results
+ * do not depend on it.  INVALID_ARG for other modes.  The plan getter
+ * returns the setting and (*used) the mode its launches use, from the
+ * workspace size once known. */
+fdtd_status fdtd_batch_set_stream_stores(fdtd_batch *batch, int32_t mode);
 fdtd_status fdtd_batch_get_tile_order(const fdtd_batch *batch, int32_t *order, int32_t *used);
 
 /* Message of the batch's last failed call; with batch == NULL, of the last
@@ -320,6 +335,8 @@ fdtd_status fdtd_plan_get_config(const fdtd_plan *plan, int32_t *tile_rows, int3
 fdtd_status fdtd_plan_set_config(fdtd_plan *plan, int32_t tile_rows, int32_t zchunk);
 fdtd_status fdtd_plan_set_tile_order(fdtd_plan *plan, int32_t order);
 fdtd_status fdtd_plan_get_tile_order(const fdtd_plan *plan, int32_t *order, int32_t *used);
+fdtd_status fdtd_plan_set_stream_stores(fdtd_plan *plan, int32_t mode);
+fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, int32_t *used);
 
 /* fdtd_batch_autotune for one bound FUSED plan that is not in a batch: the
  * same candidates, timing and cache (a plan and a one-member batch of the

@@ -180,6 +180,17 @@ def fdtd_plan_get_tile_order(plan):
     return o.value, u.value
 
 
+def fdtd_plan_set_stream_stores(plan, mode: int):
+    check(lib().fdtd_plan_set_stream_stores(plan, mode), "fdtd_plan_set_stream_stores", plan)
+
+
+def fdtd_plan_get_stream_stores(plan):
+    m, u = C.c_int32(), C.c_int32()
+    check(lib().fdtd_plan_get_stream_stores(plan, C.byref(m), C.byref(u)),
+          "fdtd_plan_get_stream_stores", plan)
+    return m.value, u.value
+
+
 def fdtd_plan_autotune(plan, trial_steps: int = 20, cache_path: Optional[str] = None,
                        stream=None) -> int:
     best = C.c_int32()
@@ -321,6 +332,12 @@ class Simulation:
     def set_tile_order(self, order: int):
         fdtd_plan_set_tile_order(self.handle, order)
 
+    def set_stream_stores(self, mode: int):
+        fdtd_plan_set_stream_stores(self.handle, mode)
+
+    def stream_stores(self):
+        return fdtd_plan_get_stream_stores(self.handle)
+
     def tile_order(self):
         return fdtd_plan_get_tile_order(self.handle)
 
@@ -402,6 +419,10 @@ class BatchSimulation:
     def set_tile_order(self, order: int):
         check(lib().fdtd_batch_set_tile_order(self.handle, order), "fdtd_batch_set_tile_order",
               self.handle, batch=True)
+
+    def set_stream_stores(self, mode: int):
+        check(lib().fdtd_batch_set_stream_stores(self.handle, mode),
+              "fdtd_batch_set_stream_stores", self.handle, batch=True)
 
     def set_group_bytes(self, nbytes: int):
         check(lib().fdtd_batch_set_group_bytes(self.handle, nbytes), "fdtd_batch_set_group_bytes",

@@ -197,6 +197,7 @@ void run_span(Batch &B, int a, int m, const TileSet *sets_dev, int32_t nb, int32
     const bool sample = B.max_probes > 0;
     LaunchCfg cfg = B.cfg;
     cfg.order = tile_order(B.cfg, state);
+    cfg.stream = stream_stores(B.cfg, state);
     for (int64_t q = 0; q < nsteps; ++q) {
         const DevGrid<float> *g = reinterpret_cast<const DevGrid<float> *>(tb + t.grids[P0.parity]) + a;
         hipEvent_t e0, e1;
@@ -393,6 +394,15 @@ fdtd_status fdtd_batch_get_groups(const fdtd_batch *batch, int32_t *ngroups)
     if (!batch || !ngroups) return FDTD_E_INVALID_ARG;
     *ngroups = (int32_t)batch->groups.size();
     return FDTD_OK;
+}
+
+fdtd_status fdtd_batch_set_stream_stores(fdtd_batch *batch, int32_t mode)
+{
+    if (!batch) return FDTD_E_INVALID_ARG;
+    return bguard(batch, [&]() {
+        BREQUIRE(mode >= -1 && mode <= 1, FDTD_E_INVALID_ARG, "stream-store mode must be -1, 0 or 1");
+        batch->cfg.stream = mode;
+    });
 }
 
 fdtd_status fdtd_batch_set_tile_order(fdtd_batch *batch, int32_t order)

@@ -77,6 +77,21 @@ __device__ __forceinline__ void gst(T *base, uint32_t idx, T v)
 __device__ __forceinline__ float ldf(const float *base, uint32_t idx) { return gld(base, idx); }
 __device__ __forceinline__ void stf(float *base, uint32_t idx, float v) { gst(base, idx, v); }
 
+// Field store of the step's output.  NT: streaming (non-temporal) store,
+// for states larger than the memory-side cache: the value is not read again
+// until the next step, so caching it only evicts this step's inputs.  For a
+// cache-resident state the plain store keeps the next step's inputs cached.
+template <bool NT>
+__device__ __forceinline__ void field_st(float *base, uint32_t idx, float v)
+{
+    if constexpr (NT) {
+        GLOBAL_AS char *b = (GLOBAL_AS char *)base;
+        __builtin_nontemporal_store(v, (GLOBAL_AS float *)(b + idx * (uint32_t)sizeof(float)));
+    } else {
+        gst(base, idx, v);
+    }
+}
+
 // One {Ca, Cb/d1, Cb/d2, 0} LUT entry as a single 16-byte global load.
 __device__ __forceinline__ float4 lut_entry(const float *lut, int id)
 {
@@ -366,7 +381,7 @@ struct MarchState {
 // caller alternates the two register sets instead of copying them: a copy
 // would have to wait for the loads in flight.  Past the end of the chunk
 // the prefetches repeat the last plane (cache hits, results unused).
-template <int X, int Y, bool LAYERS, int IDB>
+template <int X, int Y, bool LAYERS, int IDB, bool NT>
 __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<X, Y> &sm,
                                             const Tabs<X, Y> &tb, const TileCtx &t, int k,
                                             const PlaneRegs &cur, PlaneRegs &nxt, MarchState &m)
@@ -407,9 +422,9 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<X, Y> 
         if (!LAYERS || t.own)
             h_apply<X, Y, LAYERS>(d, tb, L, lx, ly, lz, df, cur.ph, true, cur.hx, cur.hy, cur.hz,
                                ox, oy, oz);
-        stf(d.Ho[0], c, ox);
-        stf(d.Ho[1], c, oy);
-        stf(d.Ho[2], c, oz);
+        field_st<NT>(d.Ho[0], c, ox);
+        field_st<NT>(d.Ho[1], c, oy);
+        field_st<NT>(d.Ho[2], c, oz);
         sm.h[0][ly][lx] = t.own ? ox : 0.f;
         sm.h[1][ly][lx] = t.own ? oy : 0.f;
         sm.h[2][ly][lx] = t.own ? oz : 0.f;
@@ -482,9 +497,9 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<X, Y> 
         const float ey = cy.x * sm.e[s0][1][ly][lx] + cy.y * dHx_z - cy.z * dHz_x;
         float ez = cz.x * sm.e[s0][2][ly][lx] + cz.y * dHy_x - cz.z * dHx_y;
         if (t.src_col && k >= d.src_box[4] && k <= d.src_box[5]) ez += t.sval;
-        stf(d.Eo[0], c, ex);
-        stf(d.Eo[1], c, ey);
-        stf(d.Eo[2], c, ez);
+        field_st<NT>(d.Eo[0], c, ex);
+        field_st<NT>(d.Eo[1], c, ey);
+        field_st<NT>(d.Eo[2], c, ez);
         m.hx_prev = hx;
         m.hy_prev = hy;
     }
@@ -497,11 +512,11 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<X, Y> 
 }
 
 // The tile of X by Y cells at (x0, y0), z-chunk tz.
-template <int X, int Y, bool LAYERS, int IDB>
+template <int X, int Y, bool LAYERS, int IDB, bool NT>
 __device__ void fused_tile(const DevGrid<float> &d, int x0, int y0, int tz, int zchunk,
                            int64_t level, Smem<X, Y> &sm, const Tabs<X, Y> &tb)
 {
-    constexpr int NT = X * Y;   // threads of the block
+    constexpr int NTH = X * Y;  // threads of the block
     TileCtx tc;
     tc.x0 = x0;
     tc.y0 = y0;
@@ -542,20 +557,20 @@ __device__ void fused_tile(const DevGrid<float> &d, int x0, int y0, int tz, int 
 
     // ---- block caches: LUTs (and the layer profiles of boundary tiles) ------
     const int nlut = d.nlut;
-    for (int q = t; q < 3 * nlut; q += NT) {
+    for (int q = t; q < 3 * nlut; q += NTH) {
         const int c = q / nlut, e = q % nlut;
         tb.lut[c * tb.cap + e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
     }
     if constexpr (LAYERS) {
-        for (int q = t; q < PR_COUNT * (X + 2); q += NT) {
+        for (int q = t; q < PR_COUNT * (X + 2); q += NTH) {
             const int tab = q / (X + 2), p = q % (X + 2);
             tb.px[q] = prof_at(d.prof[0], tab, d.nx, x0 - 1 + p);
         }
-        for (int q = t; q < PR_COUNT * (Y + 2); q += NT) {
+        for (int q = t; q < PR_COUNT * (Y + 2); q += NTH) {
             const int tab = q / (Y + 2), p = q % (Y + 2);
             tb.py[q] = prof_at(d.prof[1], tab, d.ny, y0 - 1 + p);
         }
-        for (int q = t; q < PR_COUNT * (ZMAX + 1); q += NT) {
+        for (int q = t; q < PR_COUNT * (ZMAX + 1); q += NTH) {
             const int tab = q / (ZMAX + 1), p = q % (ZMAX + 1);
             tb.pz[q] = prof_at(d.prof[2], tab, d.nz, z0 - 1 + p);
         }
@@ -618,10 +633,10 @@ __device__ void fused_tile(const DevGrid<float> &d, int x0, int y0, int tz, int 
     // odd last plane runs after the loop
     int k = z0;
     for (; k + 1 < tc.z1; k += 2) {
-        march_plane<X, Y, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
-        march_plane<X, Y, LAYERS, IDB>(d, sm, tb, tc, k + 1, rb, ra, m);
+        march_plane<X, Y, LAYERS, IDB, NT>(d, sm, tb, tc, k, ra, rb, m);
+        march_plane<X, Y, LAYERS, IDB, NT>(d, sm, tb, tc, k + 1, rb, ra, m);
     }
-    if (k < tc.z1) march_plane<X, Y, LAYERS, IDB>(d, sm, tb, tc, k, ra, rb, m);
+    if (k < tc.z1) march_plane<X, Y, LAYERS, IDB, NT>(d, sm, tb, tc, k, ra, rb, m);
 }
 
 // Tile of block b of n.  Block b is dispatched to XCD b % 8.  Order 0: each
@@ -695,7 +710,7 @@ __device__ __forceinline__ void boundary_tile(const TileSet &s, int q, int &tx, 
 template <int R, bool LAYERS>
 constexpr int min_waves() { return LAYERS ? (R >= 8 ? 4 : 1) : (R >= 4 ? 6 : 1); }
 
-template <int R, bool LAYERS, int IDB>
+template <int R, bool LAYERS, int IDB, bool NT>
 __global__ void __launch_bounds__(TW *R)
 __attribute__((amdgpu_waves_per_eu(min_waves<R, LAYERS>(), 8)))
 k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ sets, int ninst,
@@ -735,7 +750,7 @@ k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ se
             const int n = q / st, sub = n % s.nxw, rest = n / s.nxw;
             Tabs<NW, YN> tb;
             tb.place(dyn_lds, lut_cap);
-            fused_tile<NW, YN, true, IDB>(grids[lo], s.tx * TW + sub * NW, (rest % s.nty) * YN,
+            fused_tile<NW, YN, true, IDB, NT>(grids[lo], s.tx * TW + sub * NW, (rest % s.nty) * YN,
                                           rest / s.nty, zchunk, level,
                                           *reinterpret_cast<SmN *>(smraw), tb);
             return;
@@ -746,31 +761,31 @@ k_fused(const DevGrid<float> *__restrict__ grids, const TileSet *__restrict__ se
     }
     Tabs<TW, R> tb;
     tb.place(dyn_lds, lut_cap);
-    fused_tile<TW, R, LAYERS, IDB>(grids[lo], tx * TW, ty * R, tz, zchunk, level,
+    fused_tile<TW, R, LAYERS, IDB, NT>(grids[lo], tx * TW, ty * R, tz, zchunk, level,
                                    *reinterpret_cast<SmW *>(smraw), tb);
 }
 
-template <int R, bool LAYERS, int IDB>
+template <int R, bool LAYERS, int IDB, bool NT>
 hipError_t launch_r(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                     int zchunk, int64_t level, const DevProbes *probes, int nprobe_blocks,
                     int max_probes, int lut_cap, int order, hipStream_t s)
 {
-    k_fused<R, LAYERS, IDB><<<ntiles + nprobe_blocks, TW * R, tabs_bytes<R>(lut_cap, LAYERS), s>>>(
+    k_fused<R, LAYERS, IDB, NT><<<ntiles + nprobe_blocks, TW * R, tabs_bytes<R>(lut_cap, LAYERS), s>>>(
         g, sets, ninst, zchunk, ntiles, level, probes, nprobe_blocks, max_probes, lut_cap, order);
     return hipGetLastError();
 }
 
-template <bool LAYERS, int IDB>
+template <bool LAYERS, int IDB, bool NT>
 hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst, int ntiles,
                         const LaunchCfg &cfg, int64_t level, const DevProbes *probes, int npb,
                         int max_probes, int lut_cap, hipStream_t s)
 {
     switch (cfg.rows) {
-    case 2: return launch_r<2, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
-    case 4: return launch_r<4, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
-    case 8: return launch_r<8, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
-    case 12: return launch_r<12, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
-    case 16: return launch_r<16, LAYERS, IDB>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 2: return launch_r<2, LAYERS, IDB, NT>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 4: return launch_r<4, LAYERS, IDB, NT>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 8: return launch_r<8, LAYERS, IDB, NT>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 12: return launch_r<12, LAYERS, IDB, NT>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
+    case 16: return launch_r<16, LAYERS, IDB, NT>(g, sets, ninst, ntiles, cfg.zchunk, level, probes, npb, max_probes, lut_cap, cfg.order, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -783,7 +798,8 @@ hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev
                         int32_t max_probes, bool sample_input, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1)
 {
-    if (!valid_rows(cfg.rows) || cfg.order < 0 || !valid_order(cfg.order)) return hipErrorInvalidValue;
+    if (!valid_rows(cfg.rows) || cfg.order < 0 || !valid_order(cfg.order) || cfg.stream < 0)
+        return hipErrorInvalidValue;
     if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
     if (id_bits != 5 && id_bits != 8) return hipErrorInvalidValue;
     if (id_bits == 5 && lut_cap > 32) return hipErrorInvalidValue;
@@ -791,16 +807,20 @@ hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev
     if (e0) (void)hipEventRecord(e0, s);
     hipError_t err = hipSuccess;
     // the two classes write disjoint cells and read only the input level
-    if (nb + npb > 0)
-        err = id_bits == 5 ? launch_class<true, 5>(grids_dev, sets_dev, ninst, nb, cfg, level,
-                                                   probes_dev, npb, max_probes, lut_cap, s)
-                           : launch_class<true, 8>(grids_dev, sets_dev, ninst, nb, cfg, level,
-                                                   probes_dev, npb, max_probes, lut_cap, s);
-    if (err == hipSuccess && ni > 0)
-        err = id_bits == 5 ? launch_class<false, 5>(grids_dev, sets_dev, ninst, ni, cfg, level,
-                                                    probes_dev, 0, max_probes, lut_cap, s)
-                           : launch_class<false, 8>(grids_dev, sets_dev, ninst, ni, cfg, level,
-                                                    probes_dev, 0, max_probes, lut_cap, s);
+    auto launch = [&](auto layers, int32_t n, int32_t probe_blocks) {
+        constexpr bool L = decltype(layers)::value;
+        if (id_bits == 5)
+            return cfg.stream ? launch_class<L, 5, true>(grids_dev, sets_dev, ninst, n, cfg, level,
+                                                         probes_dev, probe_blocks, max_probes, lut_cap, s)
+                              : launch_class<L, 5, false>(grids_dev, sets_dev, ninst, n, cfg, level,
+                                                          probes_dev, probe_blocks, max_probes, lut_cap, s);
+        return cfg.stream ? launch_class<L, 8, true>(grids_dev, sets_dev, ninst, n, cfg, level,
+                                                     probes_dev, probe_blocks, max_probes, lut_cap, s)
+                          : launch_class<L, 8, false>(grids_dev, sets_dev, ninst, n, cfg, level,
+                                                      probes_dev, probe_blocks, max_probes, lut_cap, s);
+    };
+    if (nb + npb > 0) err = launch(std::true_type{}, nb, npb);
+    if (err == hipSuccess && ni > 0) err = launch(std::false_type{}, ni, 0);
     if (e1) (void)hipEventRecord(e1, s);
     return err;
 }

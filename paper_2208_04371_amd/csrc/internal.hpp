@@ -83,6 +83,7 @@ struct LaunchCfg {
     int32_t rows = 4;        // tile rows (y) per block of the fused kernel
     int32_t zchunk = 32;     // planes marched per block
     int32_t order = -1;      // block-to-tile order (see tile_order), -1 = automatic
+    int32_t stream = -1;     // streaming field stores (see stream_stores), -1 = automatic
 };
 
 // Blocks are dispatched to the 8 XCDs in turn.  Order 0 hands each XCD one
@@ -97,6 +98,19 @@ inline int32_t tile_order(const LaunchCfg &c, size_t state_bytes)
     return c.order >= 0 ? c.order : (state_bytes <= MALL_BYTES ? 0 : 16);
 }
 inline bool valid_order(int32_t order) { return order >= -1 && order <= 4096; }
+
+// Streaming (non-temporal) stores of the output fields pay once the state
+// clearly exceeds the memory-side cache (the outputs are next read a step
+// later); for a state inside it, or not far above it (where much of it
+// still hits), they push next step's inputs out of the cache.  Measured: a
+// 400 x ny x 80 microstrip series turns faster from 296 MiB up, but sweep
+// grids of 289 and 308 MiB turn much slower; 5-6 % faster from 365 MiB up
+// in the series, 3.5 % on a 7 GiB line.  Automatic switches at 512 MiB.
+constexpr size_t STREAM_BYTES = 2 * MALL_BYTES;
+inline int32_t stream_stores(const LaunchCfg &c, size_t state_bytes)
+{
+    return c.stream >= 0 ? c.stream : (state_bytes > STREAM_BYTES ? 1 : 0);
+}
 
 // Tile heights the fused kernel is instantiated for.
 inline bool valid_rows(int32_t rows)

@@ -692,6 +692,7 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
             const char *tab = P.base + P.r_grid.off;
             LaunchCfg cfg = P.cfg;
             cfg.order = tile_order(P.cfg, P.ws_bytes);
+            cfg.stream = stream_stores(P.cfg, P.ws_bytes);
             hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
                                    reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF), 1,
                                    P.tiles.nb, P.tiles.ni, cfg,
@@ -1107,6 +1108,22 @@ fdtd_status fdtd_plan_get_tile_order(const fdtd_plan *plan, int32_t *order, int3
     if (!plan) return FDTD_E_INVALID_ARG;
     if (order) *order = plan->cfg.order;
     if (used) *used = tile_order(plan->cfg, plan->ws_bytes);
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_plan_set_stream_stores(fdtd_plan *plan, int32_t mode)
+{
+    PLAN_GUARD(plan) {
+        REQUIRE(mode >= -1 && mode <= 1, FDTD_E_INVALID_ARG, "stream-store mode must be -1, 0 or 1");
+        plan->cfg.stream = mode;
+    });
+}
+
+fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, int32_t *used)
+{
+    if (!plan) return FDTD_E_INVALID_ARG;
+    if (mode) *mode = plan->cfg.stream;
+    if (used) *used = stream_stores(plan->cfg, plan->ws_bytes);
     return FDTD_OK;
 }
 

@@ -87,6 +87,20 @@ def test_call_order_and_argument_errors(fd):
     fd.fdtd_plan_set_tile_order(h, 16)
     assert fd.fdtd_plan_get_tile_order(h) == (16, 16)
     fd.fdtd_plan_set_tile_order(h, -1)
+    # streaming stores: -1 (automatic), 0, 1
+    assert fd.fdtd_plan_get_stream_stores(h) == (-1, 0)   # 9 MB workspace: off
+    for bad in (-2, 2):
+        with pytest.raises(fd.FdtdError) as e:
+            fd.fdtd_plan_set_stream_stores(h, bad)
+        assert e.value.code == -1
+    fd.fdtd_plan_set_stream_stores(h, 1)
+    assert fd.fdtd_plan_get_stream_stores(h) == (1, 1)
+    fd.fdtd_plan_set_stream_stores(h, -1)
+    big = describe(W.large_line(nsteps=10))
+    fdtd_plan_workspace_size(big)
+    assert fd.fdtd_plan_get_stream_stores(big) == (-1, 1)
+    assert fd.fdtd_plan_get_tile_order(big) == (-1, 16)
+    fdtd_plan_destroy(big)
     # timing stride: 0 off, n >= 1 every n-th step, negative refused
     with pytest.raises(fd.FdtdError) as e:
         fd.fdtd_plan_set_timing(h, -1)

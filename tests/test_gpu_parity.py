@@ -193,7 +193,8 @@ def test_ragged_x_column_matches_oracle(fd, nx, rows):
 
 
 def test_tile_order_changes_timing_only(fd):
-    """Any block-to-tile order gives bit-identical fields and spectra."""
+    """Any block-to-tile order, and streaming or cached field stores, give
+    bit-identical fields and spectra."""
     p = W.small_microstrip(nsteps=120, seed=3)
     ref = None
     for order in (0, 1, 7, 16):
@@ -208,11 +209,20 @@ def test_tile_order_changes_timing_only(fd):
             assert all(np.array_equal(a, b) for a, b in zip(got[0], ref[0])), order
             assert all(np.array_equal(a, b) for a, b in zip(got[1], ref[1])), order
         sim.close()
+    for stream in (0, 1):
+        sim = fd.Simulation(p, fused=True, config=(4, 4))
+        sim.set_stream_stores(stream)
+        assert sim.stream_stores() == (stream, stream)
+        sim.run()
+        assert all(np.array_equal(a, b) for a, b in zip(_fields(sim), ref[0])), stream
+        assert all(np.array_equal(a, b) for a, b in zip(sim.spectra(), ref[1])), stream
+        sim.close()
     probs = [W.small_microstrip(nsteps=60, ny=36 + 4 * q, seed=q) for q in range(3)]
     out = []
     for order in (0, 3):
         bs = fd.BatchSimulation(probs, config=(8, 4))
         bs.set_tile_order(order)
+        bs.set_stream_stores(order > 0)
         bs.run(60)
         out.append([bs.field(q, W.EZ) for q in range(3)])
         bs.close()
