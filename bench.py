@@ -171,8 +171,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported here (every box "
-              "has one GPU; DESIGN.md describes how the path would shard).", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path runs "
+              "one process on one GPU; sharding across GPUs is not built).", file=sys.stderr)
         sys.exit(2)
 
     import torch
