@@ -245,6 +245,54 @@ def test_kernel_timer_windows_cover_every_step(fd):
     sim.close()
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_anisotropic_cells_match_oracle(fd, fused):
+    """Cells of unequal sides (dy = 1.3 dx, dz = 0.8 dx) with absorbing
+    layers, a layered substrate, a strip and both probes: every per-axis
+    coefficient (curl terms, layer profiles, probe weights) differs."""
+    p = W.small_microstrip(nx=81, nsteps=400, seed=11)
+    p.dy = 1.3 * p.dx
+    p.dz = 0.8 * p.dx
+    p.fp32 = fused
+    _say(f"anisotropic cells fused={fused}")
+    o = oracle.Oracle(p).run(p.nsteps)
+    sim = fd.Simulation(p, fused=fused, precision=None if fused else fd.FP64).run()
+    if fused:
+        _check_fields(sim, o, 1e-4, norm="l2")
+        tol = 1e-4
+    else:
+        _check_fields(sim, o, 1e-10)
+        tol = 1e-10
+    Vg, Ig = sim.spectra()
+    Vo, Io = o.spectra()
+    assert _rel(Vg, Vo) < tol and _rel(Ig, Io) < tol
+    sim.close()
+
+
+def test_batch_of_ragged_grids_equals_single_runs(fd):
+    """Members whose last x column is ragged in different ways (none, one or
+    two narrow sub-columns, a partial 64-wide tile, no 64-wide tile at all),
+    run one per group with a dealt tile order and streaming stores, give the
+    bits of their single runs."""
+    probs = [W.small_microstrip(nx=nx, nsteps=120, pml=6, src_i=8, ports=(10, nx - 10), seed=q)
+             for q, nx in enumerate((30, 69, 81, 104, 128))]
+    bs = fd.BatchSimulation(probs, config=(8, 4))
+    bs.set_group_bytes(1)
+    bs.set_tile_order(3)
+    bs.set_stream_stores(1)
+    assert bs.groups() == len(probs)
+    bs.run(120)
+    for q, p in enumerate(probs):
+        s = fd.Simulation(p, fused=True, config=(8, 4)).run()
+        Vb, Ib = bs.spectra(q)
+        Vs, Is = s.spectra()
+        assert np.array_equal(Vb, Vs) and np.array_equal(Ib, Is), f"member {q} spectra"
+        for c in range(6):
+            assert np.array_equal(bs.field(q, c), s.field(c)), f"member {q} component {c}"
+        s.close()
+    bs.close()
+
+
 def test_fused_equals_plain_fp32(fd):
     p = W.small_microstrip(nsteps=300, seed=2, sigma_strip=5.8e7)
     a = fd.Simulation(p, fused=True).run()
