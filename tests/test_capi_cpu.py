@@ -244,3 +244,22 @@ def test_source_samples_validation(fd):
     h = describe(ps, fused=True)
     assert fdtd_plan_workspace_size(h) > 0
     fdtd_plan_destroy(h)
+
+
+def test_coefficient_set_limits(fd):
+    """More than 256 distinct edge coefficient sets: plain plans switch to
+    16-bit ids, fused plans (ids in LDS-indexed 8-bit fields) refuse the grid
+    with UNSUPPORTED when it is finalized."""
+    from paper_2208_04371_amd import describe, fdtd_plan_destroy, fdtd_plan_workspace_size
+    rng = np.random.default_rng(7)
+    p = W.small_microstrip(nx=40, ny=24, nz=16, nsteps=10, pml=4, src_i=6, ports=(10, 30))
+    # irregular permittivities: the averages over the cells of an edge differ
+    p.materials = [W.Material(float(e)) for e in 1.0 + 10.0 * rng.random(40)]
+    p.cells = rng.integers(0, 40, size=p.cells.shape).astype(np.uint8)
+    h = describe(p, fused=False)
+    assert fdtd_plan_workspace_size(h) > 0
+    fdtd_plan_destroy(h)
+    with pytest.raises(fd.FdtdError) as e:
+        h = describe(p, fused=True)
+        fdtd_plan_workspace_size(h)
+    assert e.value.code == -3

@@ -293,6 +293,24 @@ def test_batch_of_ragged_grids_equals_single_runs(fd):
     bs.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plain_kernels_with_16bit_ids_match_oracle(fd, prec):
+    """More than 256 distinct edge coefficient sets (40 irregular dielectrics
+    in random cells) put the plain kernels on 16-bit ids."""
+    rng = np.random.default_rng(7)
+    p = W.small_microstrip(nx=40, ny=24, nz=16, nsteps=200, pml=4, src_i=6, ports=(10, 30))
+    p.materials = [W.Material(float(e)) for e in 1.0 + 10.0 * rng.random(40)]
+    p.cells = rng.integers(0, 40, size=p.cells.shape).astype(np.uint8)
+    _say(f"16-bit ids, plain {prec}")
+    o = oracle.Oracle(p).run(p.nsteps)
+    sim = fd.Simulation(p, fused=False, precision=fd.FP64 if prec == "fp64" else fd.FP32).run()
+    if prec == "fp64":
+        _check_fields(sim, o, 1e-10)
+    else:
+        _check_fields(sim, o, 1e-4, norm="l2")
+    sim.close()
+
+
 def test_fused_equals_plain_fp32(fd):
     p = W.small_microstrip(nsteps=300, seed=2, sigma_strip=5.8e7)
     a = fd.Simulation(p, fused=True).run()
