@@ -216,6 +216,24 @@ def test_sparams_rejects_bad_input(fd):
     assert e.value.code == -1
 
 
+def test_sparams_reports_divergence(fd):
+    """A non-finite spectrum (a run that blew up) is reported as DIVERGED,
+    not turned into numbers."""
+    f = np.array([1e9, 2e9])
+    V = np.ones((2, 2), complex)
+    I = 0.02 * np.ones((2, 2), complex)
+    # a lossy, slightly mismatched 2-port: S* = [[0.1, 0.7], [0.7, 0.1]]
+    Vt = np.empty((2, 2, 2), complex)
+    Vt[0, 0] = Vt[1, 1] = 1.1
+    Vt[0, 1] = Vt[1, 0] = 0.7
+    r = fd.fdtd_sparams(f, V, I, Vt)
+    assert np.all(np.isfinite(r["S"])) and np.all(np.isfinite(r["Z0"]))
+    V[1, 0] = np.nan
+    with pytest.raises(fd.FdtdError) as e:
+        fd.fdtd_sparams(f, V, I, Vt)
+    assert e.value.code == -6
+
+
 def test_device_copy_validates_arguments(fd):
     """Argument checks of the streaming copy happen before any HIP call."""
     L = fd.lib()

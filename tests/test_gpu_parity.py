@@ -311,6 +311,25 @@ def test_plain_kernels_with_16bit_ids_match_oracle(fd, prec):
     sim.close()
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_blow_up_is_reported_as_divergence(fd, fused):
+    """Non-finite field values (NaN written into Ez, as a run that blew up
+    would hold) reach the probe sums; fdtd_get_spectra reports DIVERGED
+    instead of returning them.  Only the float values change: every index
+    and address is the same as in a normal run."""
+    p = W.small_microstrip(nsteps=60)
+    sim = fd.Simulation(p, fused=fused)
+    sim.run(5)
+    ez = sim.field(W.EZ)
+    ez[: p.nz, :, :] = np.nan
+    sim.set_field(W.EZ, ez)
+    sim.run(40)
+    with pytest.raises(fd.FdtdError) as e:
+        sim.spectra()
+    assert e.value.code == -6
+    sim.close()
+
+
 def test_fused_equals_plain_fp32(fd):
     p = W.small_microstrip(nsteps=300, seed=2, sigma_strip=5.8e7)
     a = fd.Simulation(p, fused=True).run()
