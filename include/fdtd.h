@@ -252,7 +252,10 @@ fdtd_status fdtd_batch_bind(fdtd_batch *batch, void *dptr, size_t bytes, void *s
 /* Reset every member plan. */
 fdtd_status fdtd_batch_reset(fdtd_batch *batch, void *stream);
 
-/* Advance every member plan by nsteps steps in lockstep.  Asynchronous. */
+/* Advance every member plan by nsteps steps: in lockstep, or group after
+ * group when the batch is grouped (fdtd_batch_set_group_bytes); either way
+ * all members are at the same step when the call returns.  Asynchronous.
+ * After a failure the member states are undefined until fdtd_batch_reset. */
 fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 
 /* Choose the tile height (2, 4, 8, 12, 16 rows), z-chunk (4, 8, 16, 32, 64
