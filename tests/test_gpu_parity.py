@@ -173,6 +173,14 @@ def test_fused_launch_shapes_agree(fd, rows, zchunk):
     Vs, Is = sim.spectra()
     Vr, Ir = ref.spectra()
     assert _rel(Vs[0], Vr[0]) < 1e-6 and _rel(Is[0], Ir[0]) < 1e-6
+    # the same shape with a dealt tile order and streaming stores: same bits
+    alt = fd.Simulation(p, fused=True, config=(rows, zchunk))
+    alt.set_tile_order(5)
+    alt.set_stream_stores(1)
+    alt.run()
+    assert all(np.array_equal(a, b) for a, b in zip(_fields(alt), _fields(sim)))
+    Va, Ia = alt.spectra()
+    assert np.array_equal(Va, Vs) and np.array_equal(Ia, Is)
 
 
 @pytest.mark.parametrize("nx,rows", [(30, 8), (69, 2), (69, 16), (80, 8), (81, 4), (104, 8),
