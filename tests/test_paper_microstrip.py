@@ -15,8 +15,12 @@ disperses (the measured V/I impedance rises by ~10 % up to 19 GHz) and near
     impedance and propagation factor, and with the paper's Gamma = -0.333
     to within the impedance error;
   * the delay of S*21 is the port distance over a phase velocity between
-    the quasi-static bounds c/sqrt(eps_r) and c, nearly constant in f.
+    the quasi-static bounds c/sqrt(eps_r) and c, nearly constant in f;
+  * the effective permittivity from that delay, and the per-unit-length L
+    and C, follow the Hammerstad-Jensen closed form (the paper prints no
+    eps_e; the closed form also gives the paper's 25 ohm for w/h = 5.7).
 """
+import math
 import os
 
 import numpy as np
@@ -91,6 +95,44 @@ def test_renormalized_s_follows_eq7(run):
     s11_p, s21_p = post.lossless_line_s(-1.0 / 3.0, kappa)
     assert np.max(np.abs(r["S"][band, 0, 0] - s11_p)) < 0.05
     assert np.max(np.abs(r["S"][band, 1, 0] - s21_p)) < 0.05
+
+
+def _hammerstad_jensen(u, er):
+    """Effective permittivity and impedance of a zero-thickness microstrip of
+    width/height u on a substrate er (Hammerstad and Jensen, 1980)."""
+    a = (1 + math.log((u ** 4 + (u / 52) ** 2) / (u ** 4 + 0.432)) / 49
+         + math.log(1 + (u / 18.1) ** 3) / 18.7)
+    b = 0.564 * ((er - 0.9) / (er + 3)) ** 0.053
+    ee = (er + 1) / 2 + (er - 1) / 2 * (1 + 10 / u) ** (-a * b)
+    f = 6 + (2 * math.pi - 6) * math.exp(-(30.666 / u) ** 0.7528)
+    z0 = 376.730313 / (2 * math.pi * math.sqrt(ee)) * math.log(f / u + math.sqrt(1 + 4 / u ** 2))
+    return ee, z0
+
+
+def test_line_constants_follow_hammerstad_jensen(run):
+    """The paper gives no effective permittivity; the quasi-static closed
+    form of Hammerstad and Jensen for w/h = 5.7, eps_r = 3.8 gives
+    eps_e = 3.21 and Z0 = 25.05 ohm.  The measured eps_e = (c tau / l)^2 at
+    the low end of the band and the per-unit-length L = Z_r sqrt(eps_e)/c and
+    C = sqrt(eps_e)/(c Z_r) follow it within the staircase error of a strip
+    one cell thick over a 10-cell substrate."""
+    p, V, I, r = run
+    ee_hj, z0_hj = _hammerstad_jensen(5.7, 3.8)
+    assert abs(z0_hj - 25.0) < 0.2          # the paper's 25 ohm line
+    band = (p.freqs > 1e9) & (p.freqs <= 4e9)
+    length = (p.ports[1].i - p.ports[0].i) * p.dx
+    ee = (C0 * r["tau"][band, 1, 0] / length) ** 2
+    zr = r["Zr"][band, 0].real
+    L = zr * np.sqrt(ee) / C0
+    Cp = np.sqrt(ee) / (C0 * zr)
+    L_hj = z0_hj * math.sqrt(ee_hj) / C0
+    C_hj = math.sqrt(ee_hj) / (C0 * z0_hj)
+    print(f"eps_e {np.round(ee, 3)} (HJ {ee_hj:.3f}); L {np.round(L * 1e9, 1)} nH/m "
+          f"(HJ {L_hj * 1e9:.1f}); C {np.round(Cp * 1e12, 1)} pF/m (HJ {C_hj * 1e12:.1f})",
+          flush=True)
+    assert np.all(np.abs(ee / ee_hj - 1) < 0.03)
+    assert np.all(np.abs(L / L_hj - 1) < 0.03)
+    assert np.all(np.abs(Cp / C_hj - 1) < 0.03)
 
 
 def test_delay_is_between_quasi_static_bounds(run):
