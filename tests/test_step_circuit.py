@@ -11,7 +11,9 @@ so passivity is not asserted there.  The run is long enough (9000 steps) for
 the slowest band edge to ring down: truncated DFTs break reciprocity at the
 edges, where the excitation carries little energy.
 
-GPU: the four runs as one batch reproduce the oracle's S*, S, Z0 and delay."""
+GPU: the four runs as one batch reproduce the oracle's S*, S, Z0 and delay;
+and, as the paper's convergence check asks, S* does not depend on the width
+of the exciting pulse."""
 import os
 
 import numpy as np
@@ -83,3 +85,46 @@ def test_step_circuit_batch_matches_oracle(oracle_runs):
     assert np.max(np.abs(g["Z0"] / o["Z0"] - 1)) < 5e-3
     tau_g, tau_o = g["tau"][:, 1, 0], o["tau"][:, 1, 0]
     assert np.max(np.abs(tau_g / tau_o - 1)) < 5e-3
+
+
+@pytest.mark.gpu
+def test_sparams_do_not_depend_on_the_pulse_width():
+    """The paper's convergence check (its appendix): S* of a structure may not
+    depend on the width of the eq. 3 pulse that excites it.  Two widths
+    (sigma 1.5 and 2.25 fs, peaks near 150 and 100 THz) drive the four runs
+    of the step circuit; where both pulses carry energy (spectra within
+    -40 dB of their peaks) S*, S and Z0 agree to FP32 noise."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_04371_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2208_04371_amd as fd
+    out = []
+    for sigma in (1.5e-15, 2.25e-15):
+        runs = small_step(fp32=True)
+        for p in runs.values():
+            p.source = W.Source(W.DIFF_GAUSSIAN, p.source.box, width=sigma)
+        names = list(runs)
+        bs = fd.BatchSimulation([runs[n] for n in names])
+        bs.run(runs[names[0]].nsteps)
+        spectra = {n: bs.spectra(q) for q, n in enumerate(names)}
+        bs.close()
+        p = runs["tot1"]
+        r = fd.fdtd_sparams(p.freqs, *fd.protocol_from_runs(spectra))
+        strong = np.ones(len(p.freqs), bool)
+        for n in ("inc1", "inc2"):
+            a = np.abs(spectra[n][0][0 if n == "inc1" else 1])
+            strong &= a > 1e-2 * a.max()
+        out.append((r, strong))
+    (ra, ma), (rb, mb) = out
+    band = ma & mb
+    assert band.sum() >= 6
+    dS = np.max(np.abs(ra["S_star"][band] - rb["S_star"][band]))
+    print(f"pulse-width independence over {band.sum()} frequencies: max |dS*| {dS:.2e}", flush=True)
+    assert dS < 1e-3
+    assert np.max(np.abs(ra["S"][band] - rb["S"][band])) < 1e-3
+    assert np.max(np.abs(ra["Z0"][band] / rb["Z0"][band] - 1)) < 5e-3
+    # and the reflection is real: a width-independent, non-trivial S*11
+    assert np.max(np.abs(ra["S_star"][band, 0, 0])) > 0.05
