@@ -13,7 +13,7 @@ edges, where the excitation carries little energy.
 
 GPU: the four runs as one batch reproduce the oracle's S*, S, Z0 and delay;
 and, as the paper's convergence check asks, S* does not depend on the width
-of the exciting pulse."""
+of the exciting pulse and converges under grid refinement."""
 import os
 
 import numpy as np
@@ -128,3 +128,44 @@ def test_sparams_do_not_depend_on_the_pulse_width():
     assert np.max(np.abs(ra["Z0"][band] / rb["Z0"][band] - 1)) < 5e-3
     # and the reflection is real: a width-independent, non-trivial S*11
     assert np.max(np.abs(ra["S_star"][band, 0, 0])) > 0.05
+
+
+def _refined_step(scale):
+    s = scale
+    return W.step_circuit(nx=96 * s, ny=40 * s, nz=28 * s, delta=5e-9 / s, w1=4 * s, w2=8 * s,
+                          step_x=48 * s, sub_top=8 * s, strip_t=2 * s, pml=8 * s,
+                          src_margin=12 * s, port_margin=24 * s, nsteps=9000 * s, nf=16,
+                          fp32=True, z_step=1 * s)
+
+
+@pytest.mark.gpu
+def test_sparams_converge_under_grid_refinement():
+    """The other half of the paper's convergence check: the same step circuit
+    on cells of 5, 2.5 and 1.25 nm (every feature scaled with them; the
+    finest grid is 6.9 M cells over 36 000 steps) changes its S* less under
+    the second halving than under the first, and by less than 0.03.  (Sharp
+    metal edges make the convergence about first order.)"""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_04371_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2208_04371_amd as fd
+    S = {}
+    for scale in (1, 2, 4):
+        runs = _refined_step(scale)
+        names = list(runs)
+        print(f"refinement {scale}: {runs['tot1'].nx}x{runs['tot1'].ny}x{runs['tot1'].nz}",
+              flush=True)
+        bs = fd.BatchSimulation([runs[n] for n in names])
+        bs.run(runs[names[0]].nsteps)
+        spectra = {n: bs.spectra(q) for q, n in enumerate(names)}
+        bs.close()
+        p = runs["tot1"]
+        S[scale] = fd.fdtd_sparams(p.freqs, *fd.protocol_from_runs(spectra))["S_star"]
+    d1 = np.max(np.abs(S[1] - S[2]))
+    d2 = np.max(np.abs(S[2] - S[4]))
+    print(f"max |dS*|: 5 -> 2.5 nm {d1:.4f}, 2.5 -> 1.25 nm {d2:.4f}", flush=True)
+    assert d2 < 0.6 * d1
+    assert d2 < 0.03
