@@ -511,6 +511,51 @@ def test_full_size_microstrip_window(fd):
     assert _rel(Vg, Vo) < 1e-4 and _rel(Ig, Io) < 1e-4
 
 
+def _golden(name):
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", name + "_oracle.json")) as f:
+        g = json.load(f)
+    c = lambda d: np.asarray(d["re"]) + 1j * np.asarray(d["im"])
+    return {k: (c(v) if isinstance(v, dict) else
+                np.array([c(x) for x in v]) if k in ("V", "I") else np.asarray(v))
+            for k, v in g.items() if k in ("V", "I", "S_star", "S", "Zr", "Z0", "tau", "freqs")}
+
+
+@pytest.mark.parametrize("twin,kernel", [(False, "fused"), (True, "fused"), (False, "fp64")])
+def test_full_run_matches_stored_oracle(fd, twin, kernel):
+    """The whole 20 000-step S-parameter run of the 400x120x80 microstrip
+    (literal GHz band, and its THz twin) against the oracle's stored
+    spectra and post-processed results (tests/golden, written by the CPU
+    oracle alone): the fused FP32 path within the S-parameter bars, the
+    plain FP64 kernels to rounding."""
+    name = "microstrip_400x120x80" + ("_thz" if twin else "")
+    g = _golden(name)
+    p = W.single_microstrip(twin=twin)
+    assert p.nsteps == 20000 and np.array_equal(p.freqs, g["freqs"])
+    _say(f"full run {name}, {kernel}, {p.nsteps} steps")
+    if kernel == "fused":
+        sim = fd.Simulation(p, fused=True)
+    else:
+        sim = fd.Simulation(p, fused=False, precision=fd.FP64)
+    sim.run()
+    V, I = sim.spectra()
+    sim.close()
+    r = fd.fdtd_sparams(p.freqs, *post.single_excitation_protocol(V, I))
+    ev, ei = _rel(V, g["V"]), _rel(I, g["I"])
+    ds_star = float(np.max(np.abs(r["S_star"] - g["S_star"])))
+    ds = float(np.max(np.abs(r["S"] - g["S"])))
+    dz0 = float(np.max(np.abs(r["Z0"] / g["Z0"] - 1)))
+    dtau = float(np.max(np.abs(r["tau"][:, 1, 0] / g["tau"][:, 1, 0] - 1)))
+    _say(f"  spectra V {ev:.1e} I {ei:.1e}; |dS*| {ds_star:.1e} |dS| {ds:.1e} "
+         f"Z0 {dz0:.1e} tau {dtau:.1e}")
+    if kernel == "fused":
+        assert ev < 1e-4 and ei < 1e-4
+        assert ds_star <= 1e-3 and ds <= 1e-3 and dz0 <= 5e-3 and dtau <= 5e-3
+    else:
+        assert ev < 1e-10 and ei < 1e-10
+        assert ds_star < 1e-9 and ds < 1e-9 and dz0 < 1e-9 and dtau < 1e-9
+
+
 # ---------------------------------------------------------------------------
 # the 1024x512x256 line and the 16-instance sweep at full size, in their
 # default launch shapes
