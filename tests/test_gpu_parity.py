@@ -603,3 +603,25 @@ def test_geometry_sweep_batch_matches_oracle(fd):
         Vo, Io = o.spectra()
         assert _rel(Vb, Vo) < 1e-4 and _rel(Ib, Io) < 1e-4
     bs.close()
+
+
+def test_geometry_sweep_full_run_matches_stored_oracle(fd):
+    """The 16-instance sweep as one batch over its whole 50 000 steps, in
+    the launch shape its autotuner picks: the spectra of the smallest and
+    the largest instance against the oracle's stored full runs."""
+    probs = W.geometry_sweep()
+    assert probs[0].nsteps == 50000
+    _say(f"sweep batch of {len(probs)}, autotuned, {probs[0].nsteps} steps")
+    bs = fd.BatchSimulation(probs)
+    bs.autotune(trial_steps=16)       # leaves the members reset
+    _say(f"  launch shape {bs.get_config()}, tile order {bs.tile_order()}")
+    bs.run(probs[0].nsteps)
+    for q in (0, len(probs) - 1):
+        p = probs[q]
+        g = _golden(p.name)
+        assert np.array_equal(p.freqs, g["freqs"])
+        V, I = bs.spectra(q)
+        ev, ei = _rel(V, g["V"]), _rel(I, g["I"])
+        _say(f"  instance {q} {p.nx}x{p.ny}x{p.nz}: spectra V {ev:.1e} I {ei:.1e}")
+        assert ev < 1e-4 and ei < 1e-4
+    bs.close()
