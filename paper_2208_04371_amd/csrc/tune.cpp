@@ -2,6 +2,8 @@
 // list, the timing loop and the on-disk cache of winners.
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <cstdio>
 #include <functional>
 #include <string>
@@ -73,7 +75,9 @@ void cache_store(const char *path, const std::string &key, const LaunchCfg &cfg,
     for (auto &e : entries)
         if (e.first == key) { e.second = val; found = true; }
     if (!found) entries.emplace_back(key, val);
-    const std::string tmp = std::string(path) + ".tmp";
+    // written under a per-process name, then renamed over the cache: a
+    // reader sees the old file or the new one, never a partial write
+    const std::string tmp = std::string(path) + "." + std::to_string((long)getpid()) + ".tmp";
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     std::fprintf(f, "{\n");
