@@ -1,8 +1,11 @@
-// Batches: several FP32 fused plans (uneven shapes allowed) advanced in
-// lockstep, one fused launch per step for all of them, plus one probe and
-// one DFT launch covering every instance.  This is how the per-port runs of
-// one S-matrix (Sec. II-A: one incident and one total run per driving port)
-// and the variants of a geometry sweep share the GPU.
+// Batches: several FP32 fused plans (uneven shapes allowed) advanced
+// together.  One step of all members (or of one group of consecutive
+// members, when the members' state exceeds the group budget) is one fused
+// launch pair over an instance table, with probe sampling inside the
+// boundary launch; one DFT launch per history ring folds every member's
+// samples.  This is how the per-port runs of one S-matrix (Sec. II-A: one
+// incident and one total run per driving port) and the variants of a
+// geometry sweep share the GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
