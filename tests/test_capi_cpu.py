@@ -65,6 +65,26 @@ def test_create_rejects_bad_grids(fd):
         fdtd_plan_create(10, 10, 10, -1, 1, 1, 0.9)
 
 
+def test_fused_plan_refuses_arrays_of_4_gib(fd):
+    """The fused kernels address every array with 32-bit byte offsets: a
+    grid whose field arrays would reach 4 GiB (1600 x 1024 x 660 cells:
+    4.43 GB per component) is refused as UNSUPPORTED when the plan is
+    finalized."""
+    from paper_2208_04371_amd import describe, fdtd_plan_destroy, fdtd_plan_workspace_size
+    nx, ny, nz = 1600, 1024, 660
+    p = W.Problem(name="over_4gib", nx=nx, ny=ny, nz=nz, dx=5e-9, dy=5e-9, dz=5e-9,
+                  courant=0.99, normalized=False, materials=[W.Material(1.0)],
+                  cells=np.zeros((nz, ny, nx), dtype=np.uint8),
+                  faces=(W.PEC,) * 6, freqs=np.array([1e12]), nsteps=1, fp32=True)
+    h = describe(p, fused=True)
+    try:
+        with pytest.raises(fd.FdtdError) as e:
+            fdtd_plan_workspace_size(h)
+        assert e.value.code == -3 and "4 GiB" in str(e.value)
+    finally:
+        fdtd_plan_destroy(h)
+
+
 def test_call_order_and_argument_errors(fd):
     from paper_2208_04371_amd import (describe, fdtd_plan_add_port, fdtd_plan_autotune,
                                       fdtd_plan_create, fdtd_plan_destroy,

@@ -556,6 +556,61 @@ def test_full_run_matches_stored_oracle(fd, twin, kernel):
         assert ds_star < 1e-9 and ds < 1e-9 and dz0 < 1e-9 and dtau < 1e-9
 
 
+def _largest_fused_grid(nz=600, nsteps=60):
+    """1600 x 1024 x nz cells at 5 nm: a dielectric (eps_r 4) slab under
+    vacuum, PEC ground, 10-cell absorbing layers on the other faces, and a
+    Gaussian pulse (t0 30, width 10 steps) on an Ez line near the far top
+    corner, sampled by a point probe.  At nz = 600 each field array of a
+    fused plan takes 4.03 GB, just under the 4 GiB its 32-bit byte offsets
+    allow; nz = 660 is over it."""
+    nx, ny = 1600, 1024
+    cells = np.zeros((nz, ny, nx), dtype=np.uint8)
+    cells[: nz // 4] = 1
+    src = W.Source(W.GAUSSIAN_STEPS, (nx - 40, nx - 40, ny - 40, ny - 40, nz - 45, nz - 35),
+                   t0=30, width=10)
+    return W.Problem(name=f"largest_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, dx=5e-9, dy=5e-9,
+                     dz=5e-9, courant=0.99, normalized=False,
+                     materials=[W.Material(1.0), W.Material(4.0)], cells=cells,
+                     faces=(W.CPML,) * 4 + (W.PEC, W.CPML), pml_cells=(10,) * 6, source=src,
+                     points=[W.PointProbe(W.EZ, nx - 40, ny - 40, nz - 40)],
+                     freqs=W.linear_freqs(1e12, 1e14, 8), nsteps=nsteps, fp32=True)
+
+
+def test_largest_fused_grid_light_cone(fd):
+    """The largest grid one fused plan accepts (field arrays of 4.03 GB,
+    51.5 GB of state, default launch shape, streaming stores): a 140-cell
+    window at the far top corner (the highest addresses, its absorbing
+    layers and the source) against the oracle run on that window, every
+    field component and the probe's spectra."""
+    n = 60
+    p = _largest_fused_grid(nsteps=n)
+    _say(f"largest fused grid {p.nx}x{p.ny}x{p.nz}, {n} steps, corner window")
+    sim = fd.Simulation(p, fused=True)
+    assert sim.stream_stores()[1] == 1
+    sim.run()
+    Vg, _ = sim.spectra()
+    box = (p.nx - 140, p.nx, p.ny - 140, p.ny, p.nz - 140, p.nz)
+    wp = W.window(p, box)
+    wp.points = [W.PointProbe(W.EZ, 100, 100, 100)]
+    o = oracle.Oracle(wp).run(n)
+    m = n + 2
+    full_sl = (slice(box[4] + m, None), slice(box[2] + m, None), slice(box[0] + m, None))
+    win_sl = (slice(m, None), slice(m, None), slice(m, None))
+    got = []
+    for c in range(6):
+        f = sim.field(c)
+        got.append(f[full_sl].copy())
+        del f
+    sim.close()
+    ref = [o.field(c)[win_sl] for c in range(6)]
+    assert max(np.max(np.abs(r)) for r in ref[:3]) > 0
+    errs = _field_errors(got, ref, "l2")
+    Vo, _ = o.spectra()
+    ev = _rel(Vg, Vo)
+    _say("  field errors (l2): " + " ".join(f"{e:.1e}" for e in errs) + f"; probe {ev:.1e}")
+    assert max(errs) < 1e-4 and ev < 1e-4
+
+
 # ---------------------------------------------------------------------------
 # the 1024x512x256 line and the 16-instance sweep at full size, in their
 # default launch shapes
