@@ -130,8 +130,10 @@ typedef struct {
 /* ---- plan construction (host only, no GPU work) ------------------------ */
 
 /* Create an empty plan for a grid.  *out receives the plan.
- * Errors: INVALID_ARG for non-positive sizes/spacings/courant, unknown
- * enums; UNSUPPORTED for FUSED with FP64. */
+ * Errors: INVALID_ARG for fewer than 2 cells along an axis, more than 2^34
+ * cells, non-positive spacings or courant, unknown enums; UNSUPPORTED for
+ * FUSED with FP64 (a FUSED grid whose field arrays would reach 4 GiB is
+ * refused with UNSUPPORTED when the plan is finalized). */
 fdtd_status fdtd_plan_create(const fdtd_grid *grid, fdtd_plan **out);
 
 /* Material map: cells[nz][ny][nx] (x fastest) indexes table[0..n-1].

@@ -63,6 +63,13 @@ def test_create_rejects_bad_grids(fd):
     assert e.value.code == -3
     with pytest.raises(fd.FdtdError):
         fdtd_plan_create(10, 10, 10, -1, 1, 1, 0.9)
+    # fewer than two cells along an axis
+    for dims in ((1, 1, 1), (1, 8, 8), (8, 1, 8), (8, 8, 1)):
+        with pytest.raises(fd.FdtdError) as e:
+            fdtd_plan_create(*dims, 1, 1, 1, 0.9)
+        assert e.value.code == -1
+    h = fdtd_plan_create(2, 2, 2, 1, 1, 1, 0.9)
+    fd.fdtd_plan_destroy(h)
 
 
 def test_fused_plan_refuses_arrays_of_4_gib(fd):

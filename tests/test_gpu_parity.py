@@ -556,6 +556,90 @@ def test_full_run_matches_stored_oracle(fd, twin, kernel):
         assert ds_star < 1e-9 and ds < 1e-9 and dz0 < 1e-9 and dtau < 1e-9
 
 
+def _check_groups(got, ref, tol):
+    """L2 error of each component relative to its group (E or H); a group
+    whose reference is all zero must come out exactly zero."""
+    for grp in ((0, 1, 2), (3, 4, 5)):
+        if all(np.max(np.abs(ref[c])) == 0 for c in grp):
+            assert all(np.max(np.abs(got[c])) == 0 for c in grp), grp
+            continue
+        scale = math.sqrt(sum(np.sum(ref[c] ** 2) for c in grp))
+        for c in grp:
+            assert np.linalg.norm(got[c] - ref[c]) / scale < tol, c
+
+
+def _tiny_grid(nx, ny, nz, pml, src, nsteps=30):
+    """A small grid with a dielectric lower half, absorbing layers of `pml`
+    cells on every face (PEC faces when 0) and a Gaussian pulse (t0 10,
+    width 4 steps) on the Ez edge at `src`, sampled by a point probe."""
+    faces = (W.CPML,) * 6 if pml else (W.PEC,) * 6
+    cells = np.zeros((nz, ny, nx), dtype=np.uint8)
+    cells[: max(1, nz // 2)] = 1
+    i, j, k = src
+    return W.Problem(name=f"tiny_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, dx=5e-9, dy=5e-9,
+                     dz=5e-9, courant=0.99, normalized=False,
+                     materials=[W.Material(1.0), W.Material(3.0)], cells=cells, faces=faces,
+                     pml_cells=(pml,) * 6,
+                     source=W.Source(W.GAUSSIAN_STEPS, (i, i, j, j, k, k), t0=10, width=4),
+                     points=[W.PointProbe(W.EZ, i, j, k)], freqs=W.linear_freqs(1e13, 1e15, 4),
+                     nsteps=nsteps, fp32=True)
+
+
+TINY = [((2, 2, 2), 0, (1, 1, 0)),       # the smallest grid a plan accepts
+        ((2, 3, 4), 1, (1, 1, 1)),       # one-cell layers on every face
+        ((20, 20, 20), 10, (10, 10, 10)),  # all cells in layers: no interior tile
+        ((65, 9, 5), 2, (32, 4, 2))]     # one cell past a 64-wide tile in x
+
+
+@pytest.mark.parametrize("kernel", ["fused", "fp64"])
+@pytest.mark.parametrize("dims,pml,src", TINY, ids=["2x2x2", "2x3x4", "20x20x20", "65x9x5"])
+def test_degenerate_grids_match_oracle(fd, dims, pml, src, kernel):
+    """Grids far smaller than a tile, or made of absorbing layers only,
+    after 30 steps: every field and the probe's spectra against the oracle
+    (all-zero references must come out exactly zero)."""
+    p = _tiny_grid(*dims, pml, src)
+    _say(f"degenerate grid {dims} layers {pml} {kernel}")
+    if kernel == "fused":
+        sim = fd.Simulation(p, fused=True)
+    else:
+        sim = fd.Simulation(p, fused=False, precision=fd.FP64)
+    sim.run()
+    o = oracle.Oracle(p).run(p.nsteps)
+    tol = 1e-4 if kernel == "fused" else 1e-10
+    _check_groups(_fields(sim), _fields(o), tol)
+    Vg, _ = sim.spectra()
+    Vo, _ = o.spectra()
+    assert np.max(np.abs(Vo)) > 0 and _rel(Vg, Vo) < tol
+    sim.close()
+
+
+def test_zero_and_single_steps(fd):
+    """A run of zero steps changes nothing (fields and spectra exactly zero,
+    for a plan and a batch); runs of one and two steps match the oracle."""
+    p = W.small_microstrip(nsteps=2, seed=5)
+    _say("zero, one and two steps")
+    sim = fd.Simulation(p, fused=True)
+    sim.run(0)
+    assert sim.step == 0
+    assert all(np.max(np.abs(f)) == 0 for f in _fields(sim))
+    V, I = sim.spectra()
+    assert np.max(np.abs(V)) == 0 and np.max(np.abs(I)) == 0
+    o = oracle.Oracle(p)
+    for n in (1, 2):
+        sim.run(1)
+        o.run(1)
+        assert sim.step == n
+        _check_groups(_fields(sim), _fields(o), 1e-4)
+    sim.close()
+    bs = fd.BatchSimulation([W.small_microstrip(nsteps=2, seed=5), W.small_microstrip(nsteps=2, seed=6)])
+    bs.run(0)
+    for q in range(2):
+        assert all(np.max(np.abs(bs.field(q, c))) == 0 for c in range(6))
+        V, I = bs.spectra(q)
+        assert np.max(np.abs(V)) == 0 and np.max(np.abs(I)) == 0
+    bs.close()
+
+
 def _largest_fused_grid(nz=600, nsteps=60):
     """1600 x 1024 x nz cells at 5 nm: a dielectric (eps_r 4) slab under
     vacuum, PEC ground, 10-cell absorbing layers on the other faces, and a
