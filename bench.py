@@ -291,6 +291,25 @@ def main():
             "avg_step_us": round(step_ms * 1e3, 2),
             "hbm_frac": round(bytes_b / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         bs.close()
+        # the same twelve members run one after the other as single plans
+        # (default launch shape each, kernel timer on as in the batch run),
+        # for a like-for-like comparison
+        solo = 0.0
+        for p in probs:
+            sim1 = fd.Simulation(p, fused=True)
+            sim1.run(20)
+            sim1.reset()
+            fd.fdtd_plan_set_timing(sim1.handle, TIMING_EVERY)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sim1.run(2000)
+            sim1.spectra()
+            torch.cuda.synchronize()
+            solo += time.perf_counter() - t1
+            sim1.close()
+        var["batched_fp32_12x"]["members_one_at_a_time"] = {
+            "value": round(cells_b * 2000 / solo / 1e6, 1), "unit": "Mcell-updates/s"}
+        var["batched_fp32_12x"]["vs_members_one_at_a_time"] = round(solo / dt, 3)
         # the 16-instance geometry sweep of uneven shapes with its launch
         # shape chosen by the autotuner (no cache file: searched here, and
         # the search is outside the timed region)
