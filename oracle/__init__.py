@@ -44,11 +44,25 @@ def lib():
         L.or_setup.argtypes = [C.POINTER(OrProblem), C.POINTER(OrState)]
         L.or_run.restype = C.c_int
         L.or_run.argtypes = [C.POINTER(OrProblem), C.POINTER(OrState), C.c_int64]
+        L.or_max_threads.restype = C.c_int
+        L.or_max_threads.argtypes = []
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_waveform.restype = None
         L.or_waveform.argtypes = [C.POINTER(OrProblem), C.c_int64, C.c_int64,
                                   C.POINTER(C.c_double)]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use (omp_get_max_threads)."""
+    return int(lib().or_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n threads from now on."""
+    lib().or_set_threads(int(n))
 
 
 PD = C.POINTER(C.c_double)

@@ -32,6 +32,7 @@
  * of each axis, not value by value: parity unpinned there.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -509,4 +510,14 @@ int or_run(const or_problem *p, or_state *s, int64_t nsteps)
         sample_probes(p, s, dt, n + 1);
     }
     return 0;
+}
+
+/* Size of the OpenMP team the loops above run on, and a way to change it
+ * (timing of the oracle at a stated thread count; no effect on results,
+ * since every parallel loop writes disjoint cells and the reductions only
+ * feed the optional energy record). */
+int or_max_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
 }

@@ -42,6 +42,20 @@ def test_time_step_matches_paper(key):
     assert abs(o.dt / pin["dt_s"] - 1) < pin["rel_tol"]
 
 
+def test_lowest_resolved_frequency_matches_paper():
+    """The lowest frequency a run resolves is one over its duration: the
+    paper's step counts at the oracle's time steps (cells and CFL of
+    Sec. II-B and Sec. III) give its 0.1 GHz and 50 GHz."""
+    pins = _pins()
+    pin = pins["lowest_frequency"]
+    steps = {60000: pins["dt_microstrip"], 1400000: pins["dt_cmos_line"]}
+    for n, dt_paper, f_low in pin["cases"]:
+        grid = steps[n]
+        o = oracle.Oracle(_tiny(*grid["cells_m"], courant=grid["courant"]))
+        assert abs(o.dt / dt_paper - 1) < grid["rel_tol"]
+        assert abs(1.0 / (n * o.dt) / f_low - 1) < pin["rel_tol"], (n, 1.0 / (n * o.dt), f_low)
+
+
 def _waveform_spectrum(sigma, kind=W.DIFF_GAUSSIAN, fc=0.0, bw=0.0, t0=0.0, per=200, span=12):
     # pick cubic cells so that dt = sigma / per
     dt = sigma / per
