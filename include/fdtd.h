@@ -199,6 +199,28 @@ fdtd_status fdtd_reset(fdtd_plan *plan, void *stream);
  * Errors: STATE if not bound (or bound into a batch). */
 fdtd_status fdtd_run(fdtd_plan *plan, int64_t nsteps, void *stream);
 
+/* fdtd_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid it): the same
+ * steps, probe samples and DFT folds with the same kernels and bitwise the
+ * same results, and it calls no hipMalloc, hipFree or allocating library
+ * routine.  The probe history ring (the FP64 staging between each step's
+ * port sums and the DFT fold) lives in a static device array of the library,
+ * NOALLOC_RING_BYTES = 262144 bytes per GPU (held until the process ends),
+ * instead of the plan's workspace; the caller's bound workspace still holds
+ * the fields, auxiliaries and DFT accumulators.  The ring takes
+ * nprobe * 2 * 512 * 8 bytes, so plans of up to 32 probes fit.  Every call
+ * on one GPU shares that GPU's ring, which keeps the last call's contents
+ * (each call writes every slot before reading it and folds all its samples
+ * into the accumulators before it returns): calls that overlap on one GPU
+ * (plans run concurrently on several streams or host threads) race and
+ * must be serialized by the caller.  Run the plan with the device it was
+ * bound on current.  The kernel timer (fdtd_plan_set_timing) does not cover
+ * these calls.  Asynchronous.  Errors: STATE if not bound, bound into a
+ * batch, or another device is current; INVALID_ARG if the plan's ring
+ * exceeds the static ring (more than 32 probes); HIP if the ring's address
+ * could not be obtained. */
+fdtd_status fdtd_run_noalloc(fdtd_plan *plan, int64_t nsteps, void *stream);
+
 /* Number of completed steps. */
 fdtd_status fdtd_get_step(const fdtd_plan *plan, int64_t *step);
 

@@ -116,6 +116,10 @@ def fdtd_run(plan, nsteps: int, stream=None):
     check(lib().fdtd_run(plan, int(nsteps), _stream(stream)), "fdtd_run", plan)
 
 
+def fdtd_run_noalloc(plan, nsteps: int, stream=None):
+    check(lib().fdtd_run_noalloc(plan, int(nsteps), _stream(stream)), "fdtd_run_noalloc", plan)
+
+
 def fdtd_get_step(plan) -> int:
     v = C.c_int64()
     check(lib().fdtd_get_step(plan, C.byref(v)), "fdtd_get_step", plan)

@@ -73,6 +73,7 @@ SIGNATURES = {
     "fdtd_plan_bind": (I32, [P, P, SZ, P]),
     "fdtd_reset": (I32, [P, P]),
     "fdtd_run": (I32, [P, I64, P]),
+    "fdtd_run_noalloc": (I32, [P, I64, P]),
     "fdtd_get_step": (I32, [P, C.POINTER(I64)]),
     "fdtd_get_spectra": (I32, [P, I32, PD, PD, P]),
     "fdtd_read_field": (I32, [P, I32, PD, P]),

@@ -93,6 +93,9 @@ struct LaunchCfg {
 // time: better once the state streams from HBM).  Automatic: 0 up to that
 // cache size, else 16.
 constexpr size_t MALL_BYTES = (size_t)256 << 20;
+// Static probe history ring of fdtd_run_noalloc: 32 probes x 2 signals x
+// 512 samples x 8 bytes.
+constexpr size_t NOALLOC_RING_BYTES = (size_t)256 << 10;
 inline int32_t tile_order(const LaunchCfg &c, size_t state_bytes)
 {
     return c.order >= 0 ? c.order : (state_bytes <= MALL_BYTES ? 0 : 16);
@@ -227,6 +230,8 @@ struct Plan {
     int64_t dft_n = 0;                   // last sample folded into the DFT
     int64_t sampled = 0;                 // last sample written to the history ring
     int32_t parity = 0;                  // which field buffer holds the current level
+    int32_t ring_dev = -1;               // device the plan is bound on
+    double *ring = nullptr;              // its static history ring (fdtd_run_noalloc)
     LaunchCfg cfg;
     TileSet tiles{};                     // fused plans: decomposition on the device
     LaunchCfg tiles_cfg{0, 0};           // the launch shape `tiles` was made for

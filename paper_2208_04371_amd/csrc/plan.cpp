@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <new>
 #include <stdexcept>
@@ -59,6 +60,44 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Layout of a fused plan's launch table (region r_grid).
 static constexpr size_t GRID_SET_OFF = 2 * sizeof(DevGrid<float>);
 static constexpr size_t GRID_PROBES_OFF = (GRID_SET_OFF + sizeof(TileSet) + 63) & ~size_t(63);
+// the probe table again, pointing at the static history ring of
+// fdtd_run_noalloc instead of the workspace's
+static constexpr size_t GRID_PROBES2_OFF = (GRID_PROBES_OFF + sizeof(DevProbes) + 63) & ~size_t(63);
+
+// ---------------------------------------------------------------------------
+// static history ring of the allocation-free run
+// ---------------------------------------------------------------------------
+// fdtd_run_noalloc keeps the probe history ring (the FP64 staging between
+// each step's port sums and the DFT fold) in this file-scope device array
+// instead of the caller's workspace.  Every GPU holds its own copy until the
+// process ends; in host code the name is only a stand-in, so kernels get the
+// address hipGetSymbolAddress returns for the current device (looked up
+// once per device when a plan is bound there).  No slot needs clearing: a run
+// folds every sample it writes before it returns, and writes each slot
+// before reading it.
+static __device__ __align__(256) double scratch[NOALLOC_RING_BYTES / sizeof(double)];
+
+static std::mutex g_scratch_mu;
+static std::unordered_map<int, double *> g_scratch;   // device -> address of `scratch`
+
+// Address of `scratch` on the current device (looked up once per device).
+static hipError_t scratch_ring(int &dev, double *&ptr)
+{
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        ptr = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr = static_cast<double *>(p);
+    g_scratch[dev] = ptr;
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // finalize: everything derived from the description
@@ -275,7 +314,7 @@ static void layout(Plan &P)
     take(P.r_range, std::max<size_t>(1, P.prange.size()) * 4);
     take(P.r_freq, std::max<size_t>(1, P.freqs.size()) * 8);
     take(P.r_src, std::max<size_t>(1, P.src_samples.size()) * 8);
-    take(P.r_grid, GRID_PROBES_OFF + sizeof(DevProbes) + 64);
+    take(P.r_grid, GRID_PROBES2_OFF + sizeof(DevProbes) + 64);
     P.r_static.bytes = cur;
     // mutable state
     P.r_mut.off = cur;
@@ -514,6 +553,16 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     REQUIRE(((uintptr_t)base & 255) == 0, FDTD_E_INVALID_ARG, "workspace not 256-byte aligned");
     REQUIRE(bytes >= P.ws_bytes, FDTD_E_NOMEM, "workspace smaller than fdtd_plan_workspace_size");
     P.base = base;
+    P.ring_dev = -1;
+    P.ring = nullptr;
+    {
+        int dev = -1;
+        double *ring = nullptr;
+        if (scratch_ring(dev, ring) == hipSuccess) {
+            P.ring_dev = dev;
+            P.ring = ring;
+        }
+    }
     std::vector<std::vector<char>> keep;
     if (P.g.kernel == FDTD_KERNEL_FUSED) {
         const int b = P.id_bits;
@@ -563,6 +612,9 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
         keep.emplace_back(P.r_grid.bytes, 0);
         std::memcpy(keep.back().data(), g2, sizeof g2);
         std::memcpy(keep.back().data() + GRID_PROBES_OFF, &pr, sizeof pr);
+        DevProbes pr2 = pr;
+        pr2.hist = P.ring;
+        std::memcpy(keep.back().data() + GRID_PROBES2_OFF, &pr2, sizeof pr2);
         P.tiles = make_tileset(P, P.cfg);
         P.tiles_cfg = P.cfg;
         std::memcpy(keep.back().data() + GRID_SET_OFF, &P.tiles, sizeof P.tiles);
@@ -588,10 +640,12 @@ static void reset_plan(Plan &P, hipStream_t s)
 }
 
 // Fold the samples dft_n+1 .. sampled of the history ring into the DFTs.
-static void flush_dft(Plan &P, hipStream_t s)
+static void flush_dft(Plan &P, hipStream_t s, const double *ring = nullptr)
 {
     if (P.sampled > P.dft_n) {
-        hip_check(launch_dft(dev_dft(P), P.dft_n + 1, P.sampled - P.dft_n, s), "dft");
+        DevDft d = dev_dft(P);
+        if (ring) d.hist = ring;
+        hip_check(launch_dft(d, P.dft_n + 1, P.sampled - P.dft_n, s), "dft");
         P.dft_n = P.sampled;
     }
 }
@@ -671,12 +725,15 @@ void fdtd::KernelTimer::destroy()
 
 namespace fdtd {
 
-static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
+// ring: the probe history ring to use instead of the workspace's (the
+// static one of fdtd_run_noalloc); the kernel timer is then left out.
+static void run_plan(Plan &P, int64_t nsteps, hipStream_t s, double *ring = nullptr)
 {
     REQUIRE(P.bound, FDTD_E_STATE, "plan not bound");
     REQUIRE(!P.in_batch, FDTD_E_STATE, "plan belongs to a batch; use fdtd_batch_run");
     REQUIRE(nsteps >= 0, FDTD_E_INVALID_ARG, "negative step count");
-    const DevProbes pr = dev_probes(P);
+    DevProbes pr = dev_probes(P);
+    if (ring) pr.hist = ring;
     const bool fused = P.g.kernel == FDTD_KERNEL_FUSED;
     if (fused && nsteps > 0 &&
         (P.tiles_cfg.rows != P.cfg.rows || P.tiles_cfg.zchunk != P.cfg.zchunk)) {
@@ -685,8 +742,8 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
         upload(P, Region{P.r_grid.off + GRID_SET_OFF, sizeof(TileSet)}, &P.tiles, sizeof(TileSet), s);
     }
     for (int64_t t = 0; t < nsteps; ++t) {
-        hipEvent_t e0, e1;
-        hip_check(P.timer.step(e0, e1, t == 0, t + 1 == nsteps), "timer");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (!ring) hip_check(P.timer.step(e0, e1, t == 0, t + 1 == nsteps), "timer");
         if (fused) {
             // the launch samples its input level P.step (if >= 1) as well
             const char *tab = P.base + P.r_grid.off;
@@ -698,7 +755,8 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
                                    P.tiles.nb, P.tiles.ni, cfg,
                                    std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)),
                                    P.id_bits, P.step,
-                                   reinterpret_cast<const DevProbes *>(tab + GRID_PROBES_OFF),
+                                   reinterpret_cast<const DevProbes *>(
+                                       tab + (ring ? GRID_PROBES2_OFF : GRID_PROBES_OFF)),
                                    P.nprobe(), P.nprobe() > 0, s, e0, e1),
                       "fused step");
             P.parity = 1 - P.parity;
@@ -717,14 +775,14 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s)
         P.step += 1;
         // the ring holds K samples: fold them in before the next one would
         // overwrite an unfolded slot
-        if (P.sampled - P.dft_n >= P.K - 1) flush_dft(P, s);
+        if (P.sampled - P.dft_n >= P.K - 1) flush_dft(P, s, ring);
     }
     if (fused && P.sampled < P.step) {
         // the last level of the run has not been sampled by a launch yet
         hip_check(launch_probe(P.dev_grid<float>(), pr, P.step, s), "probe");
         P.sampled = P.step;
     }
-    flush_dft(P, s);
+    flush_dft(P, s, ring);
 }
 
 // entry points for the batch code
@@ -945,6 +1003,26 @@ fdtd_status fdtd_reset(fdtd_plan *plan, void *stream)
 fdtd_status fdtd_run(fdtd_plan *plan, int64_t nsteps, void *stream)
 {
     PLAN_GUARD(plan) { run_plan(*plan, nsteps, static_cast<hipStream_t>(stream)); });
+}
+
+fdtd_status fdtd_run_noalloc(fdtd_plan *plan, int64_t nsteps, void *stream)
+{
+    PLAN_GUARD(plan) {
+        Plan &P = *plan;
+        REQUIRE(P.bound, FDTD_E_STATE, "plan not bound");
+        REQUIRE(!P.in_batch, FDTD_E_STATE, "plan belongs to a batch; use fdtd_batch_run");
+        const size_t need = (size_t)P.nprobe() * 2 * (size_t)P.K * sizeof(double);
+        REQUIRE(need <= NOALLOC_RING_BYTES, FDTD_E_INVALID_ARG,
+                "probe history ring of " + std::to_string(need) + " bytes exceeds the " +
+                    std::to_string(NOALLOC_RING_BYTES) + "-byte static ring of fdtd_run_noalloc");
+        REQUIRE(P.ring != nullptr, FDTD_E_HIP, "static ring address unavailable on the bound device");
+        int dev = -1;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        REQUIRE(dev == P.ring_dev, FDTD_E_STATE,
+                "current device " + std::to_string(dev) + " is not the device the plan was bound on (" +
+                    std::to_string(P.ring_dev) + ")");
+        run_plan(P, nsteps, static_cast<hipStream_t>(stream), P.ring);
+    });
 }
 
 fdtd_status fdtd_get_step(const fdtd_plan *plan, int64_t *step)
