@@ -365,6 +365,34 @@ fdtd_status fdtd_plan_get_tile_order(const fdtd_plan *plan, int32_t *order, int3
 fdtd_status fdtd_plan_set_stream_stores(fdtd_plan *plan, int32_t mode);
 fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, int32_t *used);
 
+/* Two-level (temporally blocked) steps of a FUSED plan.  Tiles whose cells
+ * lie at least two cells away from every absorbing layer then advance two
+ * leapfrog steps per pass over the grid (level n read once, level n+2 written
+ * once, level n+1 recomputed on a two-cell halo and kept on chip), while the
+ * other tiles take the two steps one at a time; the plan keeps a third field
+ * buffer for the intermediate level of those tiles.  This halves the field
+ * traffic of the interior tiles, which is what bounds the step on grids far
+ * larger than the memory-side cache.  The update formulas, sampling and
+ * results are those of single steps (FP32 rounding aside: the two kinds of
+ * pass may contract products differently).  Runs of an odd number of steps
+ * end with a single step.
+ * set_temporal: mode 1 on, 0 off, -1 (default) automatic: on when the plan's
+ * state with two buffers would exceed 512 MiB and its default launch shape
+ * leaves two-level tiles.  Before the plan is finalized (STATE after);
+ * INVALID_ARG for other modes; UNSUPPORTED for mode 1 on a PLAIN plan.
+ * Such plans cannot join a batch.
+ * set_temporal_config: the two-level tiles are 60 cells in x, tile_rows
+ * (8, 10 or 13) in y and zchunk (4..256) planes in z; default 13 x 16.
+ * INVALID_ARG for other values.  Takes effect at the next run.
+ * get_temporal: the mode, whether the plan was finalized with the third
+ * buffer (*used), the tile shape and the number of two-level tiles of the
+ * current launch shape (0 if none; then every step is single).  Any output
+ * may be NULL. */
+fdtd_status fdtd_plan_set_temporal(fdtd_plan *plan, int32_t mode);
+fdtd_status fdtd_plan_set_temporal_config(fdtd_plan *plan, int32_t tile_rows, int32_t zchunk);
+fdtd_status fdtd_plan_get_temporal(const fdtd_plan *plan, int32_t *mode, int32_t *used,
+                                   int32_t *tile_rows, int32_t *zchunk, int32_t *tiles);
+
 /* fdtd_batch_autotune for one bound FUSED plan that is not in a batch: the
  * same candidates, timing and cache (a plan and a one-member batch of the
  * same grid shape share a cache entry).  The plan is reset afterwards unless

@@ -195,6 +195,23 @@ def fdtd_plan_get_stream_stores(plan):
     return m.value, u.value
 
 
+def fdtd_plan_set_temporal(plan, mode: int):
+    check(lib().fdtd_plan_set_temporal(plan, mode), "fdtd_plan_set_temporal", plan)
+
+
+def fdtd_plan_set_temporal_config(plan, rows: int, zchunk: int):
+    check(lib().fdtd_plan_set_temporal_config(plan, rows, zchunk),
+          "fdtd_plan_set_temporal_config", plan)
+
+
+def fdtd_plan_get_temporal(plan):
+    """(mode, used, tile_rows, zchunk, tiles)."""
+    v = [C.c_int32() for _ in range(5)]
+    check(lib().fdtd_plan_get_temporal(plan, *[C.byref(x) for x in v]),
+          "fdtd_plan_get_temporal", plan)
+    return tuple(x.value for x in v)
+
+
 def fdtd_plan_autotune(plan, trial_steps: int = 20, cache_path: Optional[str] = None,
                        stream=None) -> int:
     best = C.c_int32()
@@ -311,12 +328,17 @@ class Simulation:
     """One plan bound to a torch-owned device workspace."""
 
     def __init__(self, prob, fused: bool = True, precision: Optional[int] = None,
-                 config=None, device: str = "cuda"):
+                 config=None, device: str = "cuda", temporal: Optional[int] = None,
+                 temporal_config=None):
         import torch
         self.prob = prob
         self.handle = describe(prob, fused=fused, precision=precision)
         if config is not None:
             fdtd_plan_set_config(self.handle, *config)
+        if temporal is not None:
+            fdtd_plan_set_temporal(self.handle, temporal)
+        if temporal_config is not None:
+            fdtd_plan_set_temporal_config(self.handle, *temporal_config)
         self.nbytes = fdtd_plan_workspace_size(self.handle)
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         fdtd_plan_bind(self.handle, self.workspace.data_ptr(), self.nbytes)
@@ -347,6 +369,10 @@ class Simulation:
 
     def get_config(self):
         return fdtd_plan_get_config(self.handle)
+
+    def temporal(self):
+        """(mode, used, tile_rows, zchunk, two-level tiles)."""
+        return fdtd_plan_get_temporal(self.handle)
 
     @property
     def step(self) -> int:

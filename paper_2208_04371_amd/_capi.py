@@ -102,6 +102,10 @@ SIGNATURES = {
     "fdtd_batch_set_group_bytes": (I32, [P, C.c_uint64]),
     "fdtd_batch_set_stream_stores": (I32, [P, I32]),
     "fdtd_plan_set_stream_stores": (I32, [P, I32]),
+    "fdtd_plan_set_temporal": (I32, [P, I32]),
+    "fdtd_plan_set_temporal_config": (I32, [P, I32, I32]),
+    "fdtd_plan_get_temporal": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
+                                     C.POINTER(I32), C.POINTER(I32)]),
     "fdtd_plan_get_stream_stores": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),
     "fdtd_batch_get_groups": (I32, [P, C.POINTER(I32)]),
     "fdtd_batch_get_tile_order": (I32, [P, C.POINTER(I32), C.POINTER(I32)]),

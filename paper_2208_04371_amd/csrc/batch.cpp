@@ -274,6 +274,9 @@ fdtd_status fdtd_batch_create(fdtd_plan *const *plans, int32_t n, fdtd_batch **o
             BREQUIRE(P->g.kernel == FDTD_KERNEL_FUSED && P->g.precision == FDTD_FP32,
                      FDTD_E_UNSUPPORTED, "batches take FP32 fused plans");
             BREQUIRE(!P->bound && !P->in_batch, FDTD_E_STATE, "plan already bound");
+            BREQUIRE(P->tb_mode != 1 && !P->tb, FDTD_E_UNSUPPORTED,
+                     "plans with two-level steps run alone, not in a batch");
+            if (!P->finalized) P->tb_mode = 0;
             plan_finalize(*P);
             b->plans.push_back(P);
             b->max_probes = std::max(b->max_probes, P->nprobe());

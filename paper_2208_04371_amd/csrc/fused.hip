@@ -790,6 +790,398 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Two-level (temporally blocked) pass over the interior tiles
+// ---------------------------------------------------------------------------
+// A block of 64 x (R+3) threads owns a tile of TB_W = 60 x R cells and
+// marches through a z-chunk, taking the fields from level n (E^n,
+// H^{n-1/2}) to level n+2 (E^{n+2}, H^{n+3/2}) in one pass: HBM sees the
+// level-n inputs read once and the level-n+2 outputs written once.  Thread
+// (lane, w) owns the column x = x0-2+lane, y = y0-2+w, so that a wavefront
+// covers one row of the tile plus two halo cells on each side.  Level n+1
+// is recomputed on the halo the second level needs (never exchanged between
+// blocks) and lives in registers and LDS only, except on the one-cell rim
+// of the two-level box and in tiles that hold probe terms, where it is also
+// written out for the single-level passes of the other tiles and the probes.
+//
+// At march position m the block computes H^{n+1/2}(m) and E^{n+1}(m), then
+// H^{n+3/2}(m-1) and E^{n+2}(m-1): the second level trails by a plane, since
+// H^{n+3/2}(m-1) needs E^{n+1}(m).  The values are right on these regions
+// (the other lanes compute values nothing uses):
+//   H^{n+1/2}:  x0-2 .. x0+60, y0-2 .. y0+R      lanes 0..62, waves 0..R+2
+//   E^{n+1}:    x0-1 .. x0+60, y0-1 .. y0+R      lanes 1..62, waves 1..R+2
+//   H^{n+3/2}:  x0-1 .. x0+59, y0-1 .. y0+R-1    lanes 1..61, waves 1..R+1
+//   E^{n+2}:    x0   .. x0+59, y0   .. y0+R-1    lanes 2..61, waves 2..R+1
+// E^n is needed on x0-2 .. x0+61, y0-2 .. y0+R+1: each thread loads its own
+// column, the first three waves the extra row y0+R+1 (one component each).
+// Update formulas and their operation order are those of the single-level
+// kernel (h_apply and the E update of march_plane).
+template <int R>
+struct TBSmem {
+    // Only the y neighbours go through LDS (x neighbours are lanes of the
+    // same wavefront), and only the two components each difference needs.
+    // E^n and E^{n+1} alternate between two slots, so each march position
+    // needs two block barriers.
+    float e0[2][2][R + 4][TW];   // Ex, Ez of E^n(m), rows y0-2 .. y0+R+1
+    float h1[2][R + 3][TW];      // Hx, Hz of H^{n+1/2}(m)
+    float e1[2][2][R + 3][TW];   // Ex, Ez of E^{n+1}(m-1)
+    float h2[2][R + 3][TW];      // Hx, Hz of H^{n+3/2}(m-1)
+    float dummy[TW];             // target of the extra-row stores of waves >= 2
+};
+
+// Value of the lane one to the right (x + 1) / left (x - 1) in the
+// wavefront (the lanes at the ends get values nothing uses).
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+// Loads of one march position, issued a position ahead.
+struct TBRegs {
+    float e[3];                // E^n(m+1), own column
+    float ex;                  // E^n(m+1) on the extra row (Ex in wave 0, Ez in the others)
+    float h[3];                // H^{n-1/2}(m), own column
+    uint32_t id;               // packed edge ids of plane m
+};
+
+// Values carried from one march position to the next.
+struct TBState {
+    float e0[3];               // E^n(m)
+    float h1p[3];              // H^{n+1/2}(m-1)
+    float e1p[3];              // E^{n+1}(m-1)
+    float h2p[2];              // Hx, Hy of H^{n+3/2}(m-2)
+    uint32_t idp;              // ids of plane m-1
+};
+
+struct TBCtx {
+    int lane, w;
+    int x, y;                  // column of the thread
+    int z0, z1;                // the tile's chunk
+    int zlast;                 // last plane of E^n the pass reads (z1 + 1)
+    uint32_t col;              // field index of (x, y) clamped into storage, plane 0
+    uint32_t xcol;             // same for the extra-row load
+    uint32_t idcol;            // id index of (x, y) clamped into the grid, plane 0
+    uint32_t sz;               // plane stride
+    int exc;                   // component of the extra-row load (0 or 2)
+    bool own;                  // (x, y) is a cell of the tile and of the box
+    bool rim_xy;               // ... on the box's x or y rim
+    bool all;                  // the tile holds probe terms
+    bool src_col;
+    int sk0, sk1;              // source planes (empty range without a source)
+    int bz0, bz1;              // the box's z range
+    float sval1, sval2;        // source values of levels n+1 and n+2
+};
+
+// What the march needs of the grid descriptor, kept in registers: the
+// first component of each field (the others follow at cstride bytes).
+struct TBPtr {
+    const float *E, *H;        // level n
+    float *Eo, *Ho;            // level n+2
+    float *Em, *Hm;            // level n+1 (rim and probe tiles)
+    const void *ids;
+    int64_t cstride;
+    uint32_t sink;
+    uint32_t idplane;          // nx * ny
+    float ch[3];
+};
+
+__device__ __forceinline__ float *comp_out(float *c0, int64_t stride, int c)
+{
+    return reinterpret_cast<float *>(reinterpret_cast<char *>(c0) + c * stride);
+}
+
+template <int R, int IDB>
+__device__ __forceinline__ void tb_load(const TBPtr &d, TBRegs &r, const TBCtx &t, int ke, int kh)
+{
+    const uint32_t pe = t.sz * (uint32_t)ke, ph = t.sz * (uint32_t)kh;
+    r.e[0] = ldf(d.E, t.col + pe);
+    r.e[1] = ldf(comp_ptr(d.E, d.cstride, 1), t.col + pe);
+    r.e[2] = ldf(comp_ptr(d.E, d.cstride, 2), t.col + pe);
+    r.ex = ldf(comp_ptr(d.E, d.cstride, t.exc), t.xcol + pe);
+    r.h[0] = ldf(d.H, t.col + ph);
+    r.h[1] = ldf(comp_ptr(d.H, d.cstride, 1), t.col + ph);
+    r.h[2] = ldf(comp_ptr(d.H, d.cstride, 2), t.col + ph);
+    r.id = (uint32_t)gld(static_cast<const IdWord<IDB> *>(d.ids), t.idcol + d.idplane * (uint32_t)kh);
+}
+
+// Ex, Ez of E^n(k) of the own column and the extra row into LDS slot q.
+template <int R>
+__device__ __forceinline__ void tb_store_e0(TBSmem<R> &sm, const TBCtx &t, int q, const float *e,
+                                            float ex)
+{
+    sm.e0[q][0][t.w][t.lane] = e[0];
+    sm.e0[q][1][t.w][t.lane] = e[2];
+    float *dst = t.w < 2 ? &sm.e0[q][t.w][R + 3][t.lane] : &sm.dummy[t.lane];
+    *dst = ex;
+}
+
+// One march position m (see the comment above k_tb).  No branch inside:
+// every phase runs at every position, and a store that does not apply (a
+// lane without an own cell, a plane outside the chunk, the positions before
+// the second level starts) goes to the sink, so the compiler's wait counts
+// follow the straight-line order of the loads.  RIM: the tile writes level
+// n+1 of its rim cells (or, in a probe tile, of all its cells).
+template <int R, int IDB, bool NT, bool RIM>
+__device__ __forceinline__ void tb_plane(const TBPtr &d, TBSmem<R> &sm, const float4 *lut, int cap,
+                                         const TBCtx &t, int m, int q, const TBRegs &cur,
+                                         TBRegs &nxt, TBState &st)
+{
+    const int lane = t.lane, w = t.w;
+    const int ym = max(w - 1, 0), yp = min(w + 1, R + 2);
+    const uint32_t sink = d.sink + (uint32_t)lane;
+    // ---- requests for position m+1 (consumed one position later) ----------
+    tb_load<R, IDB>(d, nxt, t, min(m + 2, t.zlast), min(m + 1, t.z1));
+
+    // ---- H^{n+1/2}(m) ------------------------------------------------------
+    const float ex = st.e0[0], ey = st.e0[1], ez = st.e0[2];
+    const float ezx = lane_next(ez), eyx = lane_next(ey);
+    const float h1x = cur.h[0] - d.ch[1] * (sm.e0[q][1][w + 1][lane] - ez) + d.ch[2] * (cur.e[1] - ey);
+    const float h1y = cur.h[1] - d.ch[2] * (cur.e[0] - ex) + d.ch[0] * (ezx - ez);
+    const float h1z = cur.h[2] - d.ch[0] * (eyx - ey) + d.ch[1] * (sm.e0[q][0][w + 1][lane] - ex);
+    sm.h1[0][w][lane] = h1x;
+    sm.h1[1][w][lane] = h1z;
+    lds_barrier();
+
+    // ---- E^{n+1}(m) --------------------------------------------------------
+    constexpr uint32_t IDM = (1u << IDB) - 1u;
+    float e1x, e1y, e1z;
+    {
+        const float h1zx = lane_prev(h1z), h1yx = lane_prev(h1y);
+        const float dHz_y = h1z - sm.h1[1][ym][lane];
+        const float dHy_z = h1y - st.h1p[1];
+        const float dHx_z = h1x - st.h1p[0];
+        const float dHz_x = h1z - h1zx;
+        const float dHy_x = h1y - h1yx;
+        const float dHx_y = h1x - sm.h1[0][ym][lane];
+        const float4 cx = lut[cur.id & IDM];
+        const float4 cy = lut[cap + ((cur.id >> IDB) & IDM)];
+        const float4 cz = lut[2 * cap + ((cur.id >> (2 * IDB)) & IDM)];
+        e1x = cx.x * ex + cx.y * dHz_y - cx.z * dHy_z;
+        e1y = cy.x * ey + cy.y * dHx_z - cy.z * dHz_x;
+        e1z = cz.x * ez + cz.y * dHy_x - cz.z * dHx_y;
+        // (sval1 is zero off the source columns)
+        if (m >= t.sk0 && m <= t.sk1) e1z += t.sval1;
+    }
+    // E^{n+1}(m) and E^n(m+1) into the other slots, for position m+1 (the
+    // barrier after the next H update orders them)
+    sm.e1[1 - q][0][w][lane] = e1x;
+    sm.e1[1 - q][1][w][lane] = e1z;
+    tb_store_e0<R>(sm, t, 1 - q, cur.e, cur.ex);
+    if constexpr (RIM) {
+        // level n+1 of the rim (read by the single-level passes of the
+        // neighbouring tiles) and of probe tiles (read by the probes)
+        const bool on = t.own && m >= t.z0 && m < t.z1 &&
+                        (t.all || t.rim_xy || m == t.bz0 || m == t.bz1 - 1);
+        const uint32_t c = on ? t.col + t.sz * (uint32_t)m : sink;
+        stf(d.Em, c, e1x);
+        stf(comp_out(d.Em, d.cstride, 1), c, e1y);
+        stf(comp_out(d.Em, d.cstride, 2), c, e1z);
+        stf(d.Hm, c, h1x);
+        stf(comp_out(d.Hm, d.cstride, 1), c, h1y);
+        stf(comp_out(d.Hm, d.cstride, 2), c, h1z);
+    }
+
+    // ---- H^{n+3/2}(m-1) ----------------------------------------------------
+    // (at m = 0, only in the bottom chunk of a grid without a lower layer,
+    // this is H^{n+3/2}(-1) below the grid: zero, it feeds only the
+    // tangential E edges of the ground face)
+    const bool below = m == 0;
+    const float e1pzx = lane_next(st.e1p[2]), e1pyx = lane_next(st.e1p[1]);
+    float h2x = st.h1p[0] - d.ch[1] * (sm.e1[q][1][yp][lane] - st.e1p[2]) + d.ch[2] * (e1y - st.e1p[1]);
+    float h2y = st.h1p[1] - d.ch[2] * (e1x - st.e1p[0]) + d.ch[0] * (e1pzx - st.e1p[2]);
+    float h2z = st.h1p[2] - d.ch[0] * (e1pyx - st.e1p[1]) + d.ch[1] * (sm.e1[q][0][yp][lane] - st.e1p[0]);
+    h2x = below ? 0.f : h2x;
+    h2y = below ? 0.f : h2y;
+    h2z = below ? 0.f : h2z;
+    sm.h2[0][w][lane] = h2x;
+    sm.h2[1][w][lane] = h2z;
+    // the second level's outputs: planes z0 .. z1-1
+    const uint32_t co = (t.own && m - 1 >= t.z0) ? t.col + t.sz * (uint32_t)(m - 1) : sink;
+    field_st<NT>(d.Ho, co, h2x);
+    field_st<NT>(comp_out(d.Ho, d.cstride, 1), co, h2y);
+    field_st<NT>(comp_out(d.Ho, d.cstride, 2), co, h2z);
+    lds_barrier();
+
+    // ---- E^{n+2}(m-1) ------------------------------------------------------
+    {
+        const float h2zx = lane_prev(h2z), h2yx = lane_prev(h2y);
+        const float dHz_y = h2z - sm.h2[1][ym][lane];
+        const float dHy_z = h2y - st.h2p[1];
+        const float dHx_z = h2x - st.h2p[0];
+        const float dHz_x = h2z - h2zx;
+        const float dHy_x = h2y - h2yx;
+        const float dHx_y = h2x - sm.h2[0][ym][lane];
+        const float4 cx = lut[st.idp & IDM];
+        const float4 cy = lut[cap + ((st.idp >> IDB) & IDM)];
+        const float4 cz = lut[2 * cap + ((st.idp >> (2 * IDB)) & IDM)];
+        const float e2x = cx.x * st.e1p[0] + cx.y * dHz_y - cx.z * dHy_z;
+        const float e2y = cy.x * st.e1p[1] + cy.y * dHx_z - cy.z * dHz_x;
+        float e2z = cz.x * st.e1p[2] + cz.y * dHy_x - cz.z * dHx_y;
+        if (m - 1 >= t.sk0 && m - 1 <= t.sk1) e2z += t.sval2;
+        field_st<NT>(d.Eo, co, e2x);
+        field_st<NT>(comp_out(d.Eo, d.cstride, 1), co, e2y);
+        field_st<NT>(comp_out(d.Eo, d.cstride, 2), co, e2z);
+    }
+    st.h2p[0] = h2x;
+    st.h2p[1] = h2y;
+    st.e0[0] = cur.e[0];
+    st.e0[1] = cur.e[1];
+    st.e0[2] = cur.e[2];
+    st.h1p[0] = h1x;
+    st.h1p[1] = h1y;
+    st.h1p[2] = h1z;
+    st.e1p[0] = e1x;
+    st.e1p[1] = e1y;
+    st.e1p[2] = e1z;
+    st.idp = cur.id;
+}
+
+// The march of one tile from its first position to z1.
+template <int R, int IDB, bool NT, bool RIM>
+__device__ __forceinline__ void tb_march(const TBPtr &d, TBSmem<R> &sm, const float4 *lut, int cap,
+                                         const TBCtx &t, int mfirst, TBRegs &ra, TBRegs &rb,
+                                         TBState &st)
+{
+    int m = mfirst;
+    for (; m + 1 <= t.z1; m += 2) {
+        tb_plane<R, IDB, NT, RIM>(d, sm, lut, cap, t, m, 0, ra, rb, st);
+        tb_plane<R, IDB, NT, RIM>(d, sm, lut, cap, t, m + 1, 1, rb, ra, st);
+    }
+    if (m <= t.z1) tb_plane<R, IDB, NT, RIM>(d, sm, lut, cap, t, m, 0, ra, rb, st);
+}
+
+// Occupancy: two blocks of 11 waves (8 rows) per CU need 6 waves per SIMD
+// (at most 80 VGPRs), two of 13 (10 rows) 7 (72 VGPRs); a block of 16 waves
+// (13 rows) fills 4.
+template <int R>
+constexpr int tb_min_waves() { return R >= 13 ? 4 : (R >= 10 ? 7 : 6); }
+
+template <int R, int IDB, bool NT>
+__global__ void __launch_bounds__(TW *(R + 3))
+__attribute__((amdgpu_waves_per_eu(tb_min_waves<R>(), 8)))
+k_tb(const DevGrid<float> *__restrict__ grid, const TBSet *__restrict__ set, int64_t level,
+     int lut_cap, int order)
+{
+    __shared__ __attribute__((aligned(16))) TBSmem<R> sm;
+    extern __shared__ float4 dyn_lds[];
+    const DevGrid<float> &d = *grid;
+    const TBSet s = *set;
+    // what the march reads of the descriptor, in registers: its fields are
+    // then not reloaded after each store of the march
+    TBPtr g;
+    g.E = d.E[0];
+    g.H = d.H[0];
+    g.Eo = d.Eo[0];
+    g.Ho = d.Ho[0];
+    g.Em = d.Em[0];
+    g.Hm = d.Hm[0];
+    g.ids = d.ids[0];
+    g.cstride = d.cstride;
+    g.sink = (uint32_t)d.sink;
+    g.idplane = (uint32_t)(d.nx * d.ny);
+    g.ch[0] = d.ch[0];
+    g.ch[1] = d.ch[1];
+    g.ch[2] = d.ch[2];
+    const int tl = xcd_tile(blockIdx.x, s.n, order);
+    const int tx = tl % s.ntx, ty = (tl / s.ntx) % s.nty, tz = tl / (s.ntx * s.nty);
+    const int x0 = s.x0 + tx * TB_W, y0 = s.y0 + ty * R;
+    TBCtx t;
+    t.z0 = s.z0 + tz * s.zc;
+    t.z1 = min(t.z0 + s.zc, s.z1);
+    t.zlast = t.z1 + 1;
+    t.bz0 = s.z0;
+    t.bz1 = s.z1;
+    t.lane = threadIdx.x & (TW - 1);
+    t.w = __builtin_amdgcn_readfirstlane(threadIdx.x / TW);
+    t.x = x0 - 2 + t.lane;
+    t.y = y0 - 2 + t.w;
+    t.sz = (uint32_t)(d.px * d.py);
+    // storage holds x in [-1, nx], y in [-1, ny]; the box keeps x, y >= 0
+    const int cx = min(t.x, d.nx), cy = min(t.y, d.ny);
+    t.col = (uint32_t)(d.off + cx) + (uint32_t)d.px * (uint32_t)cy;
+    t.exc = t.w == 0 ? 0 : 2;
+    t.xcol = (uint32_t)(d.off + cx) + (uint32_t)d.px * (uint32_t)min(y0 + R + 1, d.ny);
+    t.idcol = (uint32_t)min(t.x, d.nx - 1) + (uint32_t)d.nx * (uint32_t)min(t.y, d.ny - 1);
+    t.own = t.lane >= 2 && t.lane < TB_W + 2 && t.w >= 2 && t.w < R + 2 && t.x < s.x1 && t.y < s.y1;
+    t.rim_xy = t.x == s.x0 || t.x == s.x1 - 1 || t.y == s.y0 || t.y == s.y1 - 1;
+    t.all = __builtin_amdgcn_readfirstlane((int)d.tbflag[tl]) != 0;
+    const bool rim_tile = t.all || tx == 0 || tx == s.ntx - 1 || ty == 0 || ty == s.nty - 1 ||
+                          tz == 0 || tz == s.ntz - 1;
+    t.src_col = d.src_kind != 0 && t.x < d.nx && t.y < d.ny && t.x >= d.src_box[0] &&
+                t.x <= d.src_box[1] && t.y >= d.src_box[2] && t.y <= d.src_box[3];
+    t.sk0 = d.src_kind != 0 ? d.src_box[4] : 1;
+    t.sk1 = d.src_kind != 0 ? d.src_box[5] : 0;
+    t.sval1 = t.src_col ? (float)source_at(d, level + 1) : 0.f;
+    t.sval2 = t.src_col ? (float)source_at(d, level + 2) : 0.f;
+
+    // ---- the coefficient LUTs into LDS ---------------------------------------
+    constexpr int NTH = TW * (R + 3);
+    const int nlut = d.nlut;
+    for (int q = threadIdx.x; q < 3 * nlut; q += NTH) {
+        const int c = q / nlut, e = q % nlut;
+        dyn_lds[c * lut_cap + e] = lut_entry(c == 0 ? d.lut[0] : (c == 1 ? d.lut[1] : d.lut[2]), e);
+    }
+
+    // ---- prologue ------------------------------------------------------------
+    TBState st;
+    TBRegs ra, rb;
+    const int mfirst = t.z0 == 0 ? 0 : t.z0 - 1;
+    // E^n(mfirst) with its extra row, and the loads of position mfirst
+    TBRegs p0;
+    tb_load<R, IDB>(g, p0, t, mfirst, mfirst);
+    tb_load<R, IDB>(g, ra, t, mfirst + 1, mfirst);
+    st.h1p[0] = st.h1p[1] = st.h1p[2] = 0.f;
+    st.e1p[0] = st.e1p[1] = st.e1p[2] = 0.f;
+    st.h2p[0] = st.h2p[1] = 0.f;
+    st.idp = 0;
+    if (t.z0 > 0) {
+        // Hx, Hy of H^{n+1/2}(z0-2), for the z difference of E^{n+1}(z0-1)
+        const uint32_t c = t.col + t.sz * (uint32_t)(t.z0 - 2);
+        const float ex = ldf(d.E[0], c), ey = ldf(d.E[1], c), ez = ldf(d.E[2], c);
+        const float ezy = ldf(d.E[2], c + (uint32_t)d.px), ezx = ldf(d.E[2], c + 1u);
+        const float hx = ldf(d.H[0], c), hy = ldf(d.H[1], c);
+        st.h1p[0] = hx - d.ch[1] * (ezy - ez) + d.ch[2] * (p0.e[1] - ey);
+        st.h1p[1] = hy - d.ch[2] * (p0.e[0] - ex) + d.ch[0] * (ezx - ez);
+    }
+    st.e0[0] = p0.e[0];
+    st.e0[1] = p0.e[1];
+    st.e0[2] = p0.e[2];
+    tb_store_e0<R>(sm, t, 0, p0.e, p0.ex);
+    // E^{n+1}(-1) below the grid for the bottom chunk (read at m = 0)
+    sm.e1[0][0][t.w][t.lane] = 0.f;
+    sm.e1[0][1][t.w][t.lane] = 0.f;
+    lds_barrier();
+
+    if (rim_tile) tb_march<R, IDB, NT, true>(g, sm, dyn_lds, lut_cap, t, mfirst, ra, rb, st);
+    else tb_march<R, IDB, NT, false>(g, sm, dyn_lds, lut_cap, t, mfirst, ra, rb, st);
+}
+
+template <int R, int IDB, bool NT>
+hipError_t launch_tb_r(const DevGrid<float> *g, const TBSet *set, int ntiles, int64_t level,
+                       int lut_cap, int order, hipStream_t s)
+{
+    k_tb<R, IDB, NT><<<ntiles, TW * (R + 3), (size_t)lut_cap * 3 * sizeof(float4), s>>>(
+        g, set, level, lut_cap, order);
+    return hipGetLastError();
+}
+
+template <int IDB, bool NT>
+hipError_t launch_tb_rows(const DevGrid<float> *g, const TBSet *set, int ntiles, int rows,
+                          int64_t level, int lut_cap, int order, hipStream_t s)
+{
+    switch (rows) {
+    case 10: return launch_tb_r<10, IDB, NT>(g, set, ntiles, level, lut_cap, order, s);
+    case 8: return launch_tb_r<8, IDB, NT>(g, set, ntiles, level, lut_cap, order, s);
+    case 13: return launch_tb_r<13, IDB, NT>(g, set, ntiles, level, lut_cap, order, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev, int32_t ninst,
@@ -823,6 +1215,24 @@ hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev
     if (err == hipSuccess && ni > 0) err = launch(std::false_type{}, ni, 0);
     if (e1) (void)hipEventRecord(e1, s);
     return err;
+}
+
+
+hipError_t launch_tb(const DevGrid<float> *g_dev, const TBSet *set_dev, int32_t ntiles,
+                     const LaunchCfg &cfg, int32_t lut_cap, int32_t id_bits, int64_t level,
+                     hipStream_t s)
+{
+    if (!valid_tb_rows(cfg.tb_rows) || cfg.order < 0 || !valid_order(cfg.order) || cfg.stream < 0)
+        return hipErrorInvalidValue;
+    if (lut_cap < 1 || lut_cap > LUT_LDS) return hipErrorInvalidValue;
+    if (id_bits != 5 && id_bits != 8) return hipErrorInvalidValue;
+    if (id_bits == 5 && lut_cap > 32) return hipErrorInvalidValue;
+    if (ntiles <= 0) return hipSuccess;
+    if (id_bits == 5)
+        return cfg.stream ? launch_tb_rows<5, true>(g_dev, set_dev, ntiles, cfg.tb_rows, level, lut_cap, cfg.order, s)
+                          : launch_tb_rows<5, false>(g_dev, set_dev, ntiles, cfg.tb_rows, level, lut_cap, cfg.order, s);
+    return cfg.stream ? launch_tb_rows<8, true>(g_dev, set_dev, ntiles, cfg.tb_rows, level, lut_cap, cfg.order, s)
+                      : launch_tb_rows<8, false>(g_dev, set_dev, ntiles, cfg.tb_rows, level, lut_cap, cfg.order, s);
 }
 
 }  // namespace fdtd

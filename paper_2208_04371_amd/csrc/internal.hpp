@@ -43,6 +43,10 @@ template <typename T>
 struct DevGrid {
     T *E[3], *H[3];          // fields read this step
     T *Eo[3], *Ho[3];        // fields written this step (== E/H in place)
+    T *Em[3], *Hm[3];        // two-level launches: where the intermediate level
+                             // of the rim and probe tiles goes (else unused)
+    const uint8_t *tbflag;   // two-level launches: per tile, 1 = write the
+                             // intermediate level of every own cell
     const void *ids[3];      // uint8 or uint16 per edge; fused plans: ids[0] holds
                              // all three packed in one word per cell (5 bits
                              // each in a uint16 if at most 32 coefficient
@@ -82,6 +86,8 @@ struct DevProbes {
 struct LaunchCfg {
     int32_t rows = 4;        // tile rows (y) per block of the fused kernel
     int32_t zchunk = 32;     // planes marched per block
+    int32_t tb_rows = 13;    // two-level kernel: tile rows (8, 10 or 13)
+    int32_t tb_zchunk = 16;  // two-level kernel: planes marched per block (4..256)
     int32_t order = -1;      // block-to-tile order (see tile_order), -1 = automatic
     int32_t stream = -1;     // streaming field stores (see stream_stores), -1 = automatic
 };
@@ -139,6 +145,25 @@ struct TileSet {
     int32_t nxw, nty;                 // narrow sub-columns (0..2), narrow tile rows
 };
 
+// Two-level (temporally blocked) tiles: the cells [x0, x1) x [y0, y1) x
+// [z0, z1) of the interior box, whose cells lie at least two cells away
+// from every absorbing layer (and from the grid's x and y faces), cut into
+// tiles of TB_W x rows x zc cells (ragged last tiles).  They advance two
+// levels per pass; every other tile takes two single-level passes.
+constexpr int TB_W = 60;
+inline bool valid_tb_rows(int32_t r) { return r == 8 || r == 10 || r == 13; }
+struct TBSet {
+    int32_t x0, x1, y0, y1, z0, z1;
+    int32_t rows, zc;
+    int32_t ntx, nty, ntz, n;         // tiles per axis and in all (0: no two-level tiles)
+};
+// Most two-level tiles a grid can have (smallest tile shape), for the
+// per-tile flags.
+inline size_t tb_max_tiles(int nx, int ny, int nz)
+{
+    return (size_t)((nx + TB_W - 1) / TB_W) * ((ny + 7) / 8) * ((nz + 3) / 4);
+}
+
 // ---------------------------------------------------------------------------
 // host-side plan
 // ---------------------------------------------------------------------------
@@ -164,7 +189,8 @@ struct KernelTimer {
     // Events to record around the next step: a opens a window, b closes it
     // (full, or `last` step of the run); either may be null.  A window left
     // open by a run that failed is dropped at the `first` step of the next.
-    hipError_t step(hipEvent_t &a, hipEvent_t &b, bool first, bool last);
+    // (count: steps the bracketed launches advance, 2 for a two-level pass)
+    hipError_t step(hipEvent_t &a, hipEvent_t &b, bool first, bool last, int32_t count = 1);
     hipError_t drain();
     void reset();
     void destroy();
@@ -212,13 +238,19 @@ struct Plan {
     std::vector<double> tw;
     std::vector<int32_t> prange;
     int32_t K = 512;                     // probe history ring length
-    int32_t nbuf = 1;                    // field buffers (2 for ping-pong)
+    int32_t nbuf = 1;                    // field buffers (2 for ping-pong, 3 with
+                                         // two-level steps)
+    int32_t tb_mode = -1;                // two-level steps: 1 on, 0 off, -1 automatic
+    bool tb = false;                     // finalized with the third buffer
+    TBSet tbset{};                       // two-level tiles of the current launch shape
+    std::vector<uint8_t> tbflags;        // per two-level tile: holds a probe term
     size_t elt = 4;                      // bytes per field value
 
     // workspace layout (offsets relative to the bound pointer)
     Region r_ids[3], r_lut[3], r_prof[3], r_toff, r_tcomp, r_tw, r_range, r_freq, r_src;
-    Region r_E[2][3], r_H[2][3], r_psi[2][PSI_COUNT], r_hist, r_acc;
-    Region r_grid;                       // fused plans: DevGrid<float> per parity + block start
+    Region r_E[3][3], r_H[3][3], r_psi[2][PSI_COUNT], r_hist, r_acc;
+    Region r_grid;                       // fused plans: launch table (DevGrids, tile sets, probes)
+    Region r_tbflag;                     // two-level plans: per-tile flags
     Region r_static, r_mut;
     size_t ws_bytes = 0;
 
@@ -230,6 +262,8 @@ struct Plan {
     int64_t dft_n = 0;                   // last sample folded into the DFT
     int64_t sampled = 0;                 // last sample written to the history ring
     int32_t parity = 0;                  // which field buffer holds the current level
+                                         // (0..nbuf-1); the H auxiliaries of the
+                                         // current level are in copy (step & 1)
     int32_t ring_dev = -1;               // device the plan is bound on
     double *ring = nullptr;              // its static history ring (fdtd_run_noalloc)
     LaunchCfg cfg;
@@ -243,6 +277,10 @@ struct Plan {
     int nprobe() const { return (int)(ports.size() + points.size()); }
     int nf() const { return (int)freqs.size(); }
     template <typename T> DevGrid<T> dev_grid() const;
+    // Single-level step from field buffer `cur` (into the next one) with
+    // the H auxiliaries of copy pp; two-level pass from buffer cur.
+    DevGrid<float> dev_grid_at(int cur, int pp) const;
+    DevGrid<float> dev_grid_tb(int cur) const;
 };
 
 struct Batch {
@@ -298,12 +336,21 @@ hipError_t launch_fused(const DevGrid<float> *grids_dev, const TileSet *sets_dev
                         int32_t id_bits, int64_t level, const DevProbes *probes_dev,
                         int32_t max_probes, bool sample_input, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1);
+// Two-level pass over the tiles of `set`: reads levels n (`level`) from
+// g.E/g.H, writes level n+2 to g.Eo/g.Ho and level n+1 of the rim and probe
+// tiles to g.Em/g.Hm.
+hipError_t launch_tb(const DevGrid<float> *g_dev, const TBSet *set_dev, int32_t ntiles,
+                     const LaunchCfg &cfg, int32_t lut_cap, int32_t id_bits, int64_t level,
+                     hipStream_t s);
 hipError_t launch_probe_batch(const DevGrid<float> *grids_dev, const DevProbes *probes_dev,
                               int32_t ninst, int32_t max_probes, int64_t sample, hipStream_t s);
 hipError_t launch_dft_batch(const DevDft *dft_dev, int32_t ninst, int32_t max_probes,
                             int32_t max_nf, int64_t n_first, int64_t count, hipStream_t s);
 // Tile decomposition of grid P under cfg (sb, si left zero).
 TileSet make_tileset(const Plan &P, const LaunchCfg &cfg);
+// Two-level tiles of P under cfg; shrinks the interior box of t (made by
+// make_tileset with cfg) to the tiles whose two-cell margin avoids the layers.
+TBSet make_tbset(const Plan &P, const LaunchCfg &cfg, TileSet &t);
 // Default launch shape for one step of the given grids.
 LaunchCfg default_launch(const Plan *const *plans, size_t n);
 

@@ -57,9 +57,14 @@ static fdtd_status guarded(Plan *p, F &&f)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Layout of a fused plan's launch table (region r_grid).
-static constexpr size_t GRID_SET_OFF = 2 * sizeof(DevGrid<float>);
-static constexpr size_t GRID_PROBES_OFF = (GRID_SET_OFF + sizeof(TileSet) + 63) & ~size_t(63);
+// Layout of a fused plan's launch table (region r_grid): the descriptors of
+// a single-level step from each field buffer with each copy of the H
+// auxiliaries (index 2 * buffer + copy), those of a two-level pass from each
+// buffer, the tile decomposition, the two-level tiles, the probes.
+static constexpr size_t GRID_TB_OFF = 6 * sizeof(DevGrid<float>);
+static constexpr size_t GRID_SET_OFF = 9 * sizeof(DevGrid<float>);
+static constexpr size_t GRID_TBSET_OFF = (GRID_SET_OFF + sizeof(TileSet) + 63) & ~size_t(63);
+static constexpr size_t GRID_PROBES_OFF = (GRID_TBSET_OFF + sizeof(TBSet) + 63) & ~size_t(63);
 // the probe table again, pointing at the static history ring of
 // fdtd_run_noalloc instead of the workspace's
 static constexpr size_t GRID_PROBES2_OFF = (GRID_PROBES_OFF + sizeof(DevProbes) + 63) & ~size_t(63);
@@ -315,6 +320,7 @@ static void layout(Plan &P)
     take(P.r_freq, std::max<size_t>(1, P.freqs.size()) * 8);
     take(P.r_src, std::max<size_t>(1, P.src_samples.size()) * 8);
     take(P.r_grid, GRID_PROBES2_OFF + sizeof(DevProbes) + 64);
+    take(P.r_tbflag, P.tb ? tb_max_tiles(P.g.nx, P.g.ny, P.g.nz) : 1);
     P.r_static.bytes = cur;
     // mutable state
     P.r_mut.off = cur;
@@ -326,11 +332,15 @@ static void layout(Plan &P)
     // ping-pong only for the H auxiliaries: tile halos read those of
     // neighbouring cells, while an E auxiliary is read and written by the
     // thread that owns its cell alone, so it is updated in place
-    for (int b = 0; b < P.nbuf; ++b)
+    // (two copies at most: with three field buffers the H auxiliaries still
+    // alternate level by level, and only the single-level passes use them)
+    for (int b = 0; b < std::min(P.nbuf, 2); ++b)
         for (int q = 0; q < PSI_COUNT; ++q) {
             if (b > 0 && q >= PSI_EXY) P.r_psi[b][q] = P.r_psi[0][q];
             else take(P.r_psi[b][q], std::max<size_t>(1, P.psi_elems[q]) * elt);
         }
+    if (P.nbuf == 1)
+        for (int q = 0; q < PSI_COUNT; ++q) P.r_psi[1][q] = P.r_psi[0][q];
     // the components of every field sit at one fixed stride (E and H interleave)
     P.cstride = P.r_E[0][1].off - P.r_E[0][0].off;
     for (int b = 0; b < P.nbuf; ++b)
@@ -390,7 +400,23 @@ static void finalize(Plan &P)
             "the fused kernel supports at most 256 distinct edge coefficients");
     for (int a = 0; a < 3; ++a) build_profiles(P, a);
     build_probes(P);
+    // two-level steps need a third field buffer: on request, or (automatic)
+    // for a state that streams from HBM (beyond twice the memory-side
+    // cache) whose default launch shape leaves two-level tiles
+    P.tb = false;
     layout(P);
+    if (g.kernel == FDTD_KERNEL_FUSED && P.tb_mode != 0) {
+        bool want = P.tb_mode == 1;
+        if (P.tb_mode < 0 && P.ws_bytes > STREAM_BYTES) {
+            TileSet t = make_tileset(P, P.cfg);
+            want = make_tbset(P, P.cfg, t).n > 0;
+        }
+        if (want) {
+            P.tb = true;
+            P.nbuf = 3;
+            layout(P);
+        }
+    }
     P.finalized = true;
 }
 
@@ -398,20 +424,26 @@ template <typename T>
 DevGrid<T> Plan::dev_grid() const
 {
     DevGrid<T> d{};
-    const int b = parity, o = nbuf == 2 ? 1 - parity : parity;
+    const int b = parity, o = nbuf == 2 ? 1 - parity : (nbuf == 3 ? (parity + 1) % 3 : parity);
+    // H auxiliaries: copy (step & 1) with three field buffers
+    const int pb = nbuf == 3 ? (int)(step & 1) : (nbuf == 2 ? b : 0);
+    const int po = nbuf == 1 ? pb : 1 - pb;
     for (int c = 0; c < 3; ++c) {
         d.E[c] = reinterpret_cast<T *>(base + r_E[b][c].off);
         d.H[c] = reinterpret_cast<T *>(base + r_H[b][c].off);
         d.Eo[c] = reinterpret_cast<T *>(base + r_E[o][c].off);
         d.Ho[c] = reinterpret_cast<T *>(base + r_H[o][c].off);
+        d.Em[c] = d.Eo[c];
+        d.Hm[c] = d.Ho[c];
         d.ids[c] = base + r_ids[c].off;
         d.lut[c] = reinterpret_cast<const T *>(base + r_lut[c].off);
         d.prof[c] = reinterpret_cast<const T *>(base + r_prof[c].off);
     }
     for (int q = 0; q < PSI_COUNT; ++q) {
-        d.psi[q] = reinterpret_cast<T *>(base + r_psi[b][q].off);
-        d.psi_o[q] = reinterpret_cast<T *>(base + r_psi[o][q].off);
+        d.psi[q] = reinterpret_cast<T *>(base + r_psi[pb][q].off);
+        d.psi_o[q] = reinterpret_cast<T *>(base + r_psi[po][q].off);
     }
+    d.tbflag = reinterpret_cast<const uint8_t *>(base + r_tbflag.off);
     d.off = 64 + (int64_t)px * (1 + py);
     d.cstride = (int64_t)cstride;
     d.sink = (int64_t)sink;
@@ -437,6 +469,39 @@ DevGrid<T> Plan::dev_grid() const
         d.src_t0 = src.t0 > 0 ? src.t0 : 3.0 * src.width;
     else
         d.src_t0 = src.t0;
+    return d;
+}
+
+DevGrid<float> Plan::dev_grid_at(int cur, int pp) const
+{
+    DevGrid<float> d = dev_grid<float>();
+    const int o = nbuf == 1 ? cur : (cur + 1) % nbuf;
+    for (int c = 0; c < 3; ++c) {
+        d.E[c] = reinterpret_cast<float *>(base + r_E[cur][c].off);
+        d.H[c] = reinterpret_cast<float *>(base + r_H[cur][c].off);
+        d.Eo[c] = reinterpret_cast<float *>(base + r_E[o][c].off);
+        d.Ho[c] = reinterpret_cast<float *>(base + r_H[o][c].off);
+        d.Em[c] = d.Eo[c];
+        d.Hm[c] = d.Ho[c];
+    }
+    const int po = nbuf == 1 ? pp : 1 - pp;
+    for (int q = 0; q < PSI_COUNT; ++q) {
+        d.psi[q] = reinterpret_cast<float *>(base + r_psi[pp][q].off);
+        d.psi_o[q] = reinterpret_cast<float *>(base + r_psi[po][q].off);
+    }
+    return d;
+}
+
+DevGrid<float> Plan::dev_grid_tb(int cur) const
+{
+    DevGrid<float> d = dev_grid_at(cur % nbuf, 0);
+    const int m = (cur + 1) % nbuf, o = (cur + 2) % nbuf;
+    for (int c = 0; c < 3; ++c) {
+        d.Em[c] = reinterpret_cast<float *>(base + r_E[m][c].off);
+        d.Hm[c] = reinterpret_cast<float *>(base + r_H[m][c].off);
+        d.Eo[c] = reinterpret_cast<float *>(base + r_E[o][c].off);
+        d.Ho[c] = reinterpret_cast<float *>(base + r_H[o][c].off);
+    }
     return d;
 }
 
@@ -499,6 +564,60 @@ TileSet make_tileset(const Plan &P, const LaunchCfg &cfg)
     return t;
 }
 
+// Two-level tiles for the tile decomposition t (made by make_tileset with the
+// same cfg).  The two-level pass recomputes two cells around every cell it
+// writes, so the box of interior tiles is shrunk, a tile row or plane at a
+// time, until that margin avoids the absorbing layers and the grid's x and y
+// faces and the planes it reads exist: x0 - 2 >= lo, x1 + 2 <= n - hi (also
+// y), and z0 = 0 on a grid without a lower z layer or z0 - 2 >= lo, and
+// z1 + 1 <= nz - hi.  The tiles taken off join the boundary launch.  Returns
+// the cell box cut into TB_W x cfg.tb_rows x cfg.tb_zchunk tiles (n = 0
+// when none is left).
+TBSet make_tbset(const Plan &P, const LaunchCfg &cfg, TileSet &t)
+{
+    const int n[3] = {P.g.nx, P.g.ny, P.g.nz};
+    const int w[3] = {64, cfg.rows, cfg.zchunk};
+    int *b0[3] = {&t.ix0, &t.iy0, &t.iz0}, *b1[3] = {&t.ix1, &t.iy1, &t.iz1};
+    int c0[3], c1[3];
+    for (int a = 0; a < 3; ++a) {
+        auto lo_ok = [&](int q) {
+            const int c = q * w[a];
+            if (a == 2 && c == 0) return P.lo[2] == 0;
+            return c - 2 >= P.lo[a];
+        };
+        auto hi_ok = [&](int q) {
+            const int c = std::min(q * w[a], n[a]);
+            return a == 2 ? c + 1 <= n[a] - P.hi[a] : c + 2 <= n[a] - P.hi[a];
+        };
+        while (*b0[a] < *b1[a] && !lo_ok(*b0[a])) ++*b0[a];
+        while (*b0[a] < *b1[a] && !hi_ok(*b1[a])) --*b1[a];
+        c0[a] = *b0[a] * w[a];
+        c1[a] = std::min(*b1[a] * w[a], n[a]);
+    }
+    if (t.ix0 >= t.ix1 || t.iy0 >= t.iy1 || t.iz0 >= t.iz1) {
+        t.ix0 = t.ix1 = t.iy0 = t.iy1 = t.iz0 = t.iz1 = 0;
+        c0[0] = c1[0] = c0[1] = c1[1] = c0[2] = c1[2] = 0;
+    }
+    const int rx = P.g.nx % 64;
+    const int cntx = (rx > 0 && rx <= 32) ? n[0] / 64 : (n[0] + 63) / 64;
+    const int cnty = (n[1] + w[1] - 1) / w[1], cntz = (n[2] + w[2] - 1) / w[2];
+    t.ni = (t.ix1 - t.ix0) * (t.iy1 - t.iy0) * (t.iz1 - t.iz0);
+    t.nb = cntx * cnty * cntz - t.ni + t.nxw * t.nty * cntz;
+    TBSet b{};
+    b.x0 = c0[0]; b.x1 = c1[0];
+    b.y0 = c0[1]; b.y1 = c1[1];
+    b.z0 = c0[2]; b.z1 = c1[2];
+    b.rows = cfg.tb_rows;
+    b.zc = cfg.tb_zchunk;
+    if (t.ni > 0) {
+        b.ntx = (b.x1 - b.x0 + TB_W - 1) / TB_W;
+        b.nty = (b.y1 - b.y0 + b.rows - 1) / b.rows;
+        b.ntz = (b.z1 - b.z0 + b.zc - 1) / b.zc;
+        b.n = b.ntx * b.nty * b.ntz;
+    }
+    return b;
+}
+
 static DevProbes dev_probes(const Plan &P)
 {
     DevProbes p{};
@@ -544,6 +663,43 @@ static void upload_real(Plan &P, const Region &r, const std::vector<double> &v, 
     float *f = reinterpret_cast<float *>(keep.back().data());
     for (size_t q = 0; q < v.size(); ++q) f[q] = (float)v[q];
     upload(P, r, f, v.size() * 4, s);
+}
+
+// Tile decomposition of the plan's launch shape; with three field buffers
+// also the two-level tiles and, per two-level tile, whether it holds a
+// probe term (such a tile writes the intermediate level of all its cells,
+// for the probes of that level).
+static void plan_tiles(Plan &P)
+{
+    P.tiles = make_tileset(P, P.cfg);
+    P.tbset = TBSet{};
+    P.tbflags.assign(1, 0);
+    if (P.tb) {
+        P.tbset = make_tbset(P, P.cfg, P.tiles);
+        const TBSet &b = P.tbset;
+        P.tbflags.assign((size_t)std::max(1, b.n), 0);
+        REQUIRE(P.tbflags.size() <= P.r_tbflag.bytes, FDTD_E_INVALID_ARG,
+                "two-level tile shape too small for the plan");
+        const int64_t off = 64 + (int64_t)P.px * (1 + P.py);
+        const int64_t plane = (int64_t)P.px * P.py;
+        for (size_t q = 0; q < P.toff.size() && b.n > 0; ++q) {
+            const int64_t u = P.toff[q] - off + 1 + P.px + plane;
+            const int i = (int)(u % P.px) - 1, j = (int)((u / P.px) % P.py) - 1,
+                      k = (int)(u / plane) - 1;
+            if (i < b.x0 || i >= b.x1 || j < b.y0 || j >= b.y1 || k < b.z0 || k >= b.z1) continue;
+            const int tx = (i - b.x0) / TB_W, ty = (j - b.y0) / b.rows, tz = (k - b.z0) / b.zc;
+            P.tbflags[(size_t)tx + (size_t)b.ntx * (ty + (size_t)b.nty * tz)] = 1;
+        }
+    }
+    P.tiles_cfg = P.cfg;
+}
+
+// The tile sets and flags of plan_tiles into the launch table.
+static void upload_tiles(Plan &P, hipStream_t s)
+{
+    upload(P, Region{P.r_grid.off + GRID_SET_OFF, sizeof(TileSet)}, &P.tiles, sizeof(TileSet), s);
+    upload(P, Region{P.r_grid.off + GRID_TBSET_OFF, sizeof(TBSet)}, &P.tbset, sizeof(TBSet), s);
+    if (P.tb) upload(P, P.r_tbflag, P.tbflags.data(), P.tbflags.size(), s);
 }
 
 static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
@@ -598,27 +754,25 @@ static void bind_plan(Plan &P, char *base, size_t bytes, hipStream_t s)
     upload(P, P.r_freq, P.freqs.data(), P.freqs.size() * 8, s);
     upload(P, P.r_src, P.src_samples.data(), P.src_samples.size() * 8, s);
     if (P.g.kernel == FDTD_KERNEL_FUSED) {
-        // launch table of the fused kernel: the descriptors of both buffer
-        // parities, the tile decomposition (written before each run whose
-        // launch shape differs from the uploaded one) and the probes
-        DevGrid<float> g2[2];
-        const int par = P.parity;
-        for (int q = 0; q < 2; ++q) {
-            P.parity = q;
-            g2[q] = P.dev_grid<float>();
-        }
-        P.parity = par;
+        // launch table of the fused kernels: the descriptors of every step
+        // (single-level from each buffer with each auxiliary copy, two-level
+        // from each buffer), the tile sets (written again before each run
+        // whose launch shape differs from the uploaded one) and the probes
+        DevGrid<float> g9[9];
+        for (int q = 0; q < 6; ++q) g9[q] = P.dev_grid_at((q / 2) % P.nbuf, q % 2);
+        for (int q = 0; q < 3; ++q) g9[6 + q] = P.dev_grid_tb(q % P.nbuf);
         const DevProbes pr = dev_probes(P);
         keep.emplace_back(P.r_grid.bytes, 0);
-        std::memcpy(keep.back().data(), g2, sizeof g2);
+        std::memcpy(keep.back().data(), g9, sizeof g9);
         std::memcpy(keep.back().data() + GRID_PROBES_OFF, &pr, sizeof pr);
         DevProbes pr2 = pr;
         pr2.hist = P.ring;
         std::memcpy(keep.back().data() + GRID_PROBES2_OFF, &pr2, sizeof pr2);
-        P.tiles = make_tileset(P, P.cfg);
-        P.tiles_cfg = P.cfg;
+        plan_tiles(P);
         std::memcpy(keep.back().data() + GRID_SET_OFF, &P.tiles, sizeof P.tiles);
+        std::memcpy(keep.back().data() + GRID_TBSET_OFF, &P.tbset, sizeof P.tbset);
         upload(P, P.r_grid, keep.back().data(), P.r_grid.bytes, s);
+        if (P.tb) upload(P, P.r_tbflag, P.tbflags.data(), P.tbflags.size(), s);
     }
     hip_check(hipMemsetAsync(P.base + P.r_mut.off, 0, P.r_mut.bytes, s), "clear state");
     hip_check(hipStreamSynchronize(s), "bind sync");
@@ -652,7 +806,8 @@ static void flush_dft(Plan &P, hipStream_t s, const double *ring = nullptr)
 
 }  // namespace fdtd
 
-hipError_t fdtd::KernelTimer::step(hipEvent_t &a, hipEvent_t &b, bool first, bool last)
+hipError_t fdtd::KernelTimer::step(hipEvent_t &a, hipEvent_t &b, bool first, bool last,
+                                   int32_t count)
 {
     a = b = nullptr;
     if (!on) return hipSuccess;
@@ -681,7 +836,7 @@ hipError_t fdtd::KernelTimer::step(hipEvent_t &a, hipEvent_t &b, bool first, boo
         in_window = 0;
         a = ev[2 * open];
     }
-    in_window += 1;
+    in_window += count;
     if (in_window >= every || last) {
         b = ev[2 * open + 1];
         used[open] = in_window;
@@ -736,30 +891,52 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s, double *ring = null
     if (ring) pr.hist = ring;
     const bool fused = P.g.kernel == FDTD_KERNEL_FUSED;
     if (fused && nsteps > 0 &&
-        (P.tiles_cfg.rows != P.cfg.rows || P.tiles_cfg.zchunk != P.cfg.zchunk)) {
-        P.tiles = make_tileset(P, P.cfg);
-        P.tiles_cfg = P.cfg;
-        upload(P, Region{P.r_grid.off + GRID_SET_OFF, sizeof(TileSet)}, &P.tiles, sizeof(TileSet), s);
+        (P.tiles_cfg.rows != P.cfg.rows || P.tiles_cfg.zchunk != P.cfg.zchunk ||
+         P.tiles_cfg.tb_rows != P.cfg.tb_rows || P.tiles_cfg.tb_zchunk != P.cfg.tb_zchunk)) {
+        plan_tiles(P);
+        upload_tiles(P, s);
     }
-    for (int64_t t = 0; t < nsteps; ++t) {
+    const char *tab = P.base + P.r_grid.off;
+    const auto *grids = reinterpret_cast<const DevGrid<float> *>(tab);
+    const auto *tset = reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF);
+    const auto *probes = reinterpret_cast<const DevProbes *>(tab + (ring ? GRID_PROBES2_OFF : GRID_PROBES_OFF));
+    const int32_t lut_cap = std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4));
+    LaunchCfg cfg = P.cfg;
+    cfg.order = tile_order(P.cfg, P.ws_bytes);
+    cfg.stream = stream_stores(P.cfg, P.ws_bytes);
+    for (int64_t t = 0; t < nsteps;) {
+        // two levels per pass where the plan has two-level tiles
+        const bool pair = fused && P.tb && P.tbset.n > 0 && nsteps - t >= 2;
+        const int adv = pair ? 2 : 1;
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (!ring) hip_check(P.timer.step(e0, e1, t == 0, t + 1 == nsteps), "timer");
-        if (fused) {
+        if (!ring) hip_check(P.timer.step(e0, e1, t == 0, t + adv >= nsteps, adv), "timer");
+        if (pair) {
+            // boundary tiles n -> n+1 into the next buffer (sampling level
+            // n), the two-level pass n -> n+2 of the interior tiles (level
+            // n+1 of its rim and probe tiles into the next buffer too), then
+            // the boundary tiles n+1 -> n+2 (sampling level n+1)
+            const int cur = P.parity, pp = (int)(P.step & 1), mid = (cur + 1) % 3;
+            hip_check(launch_fused(grids + 2 * cur + pp, tset, 1, P.tiles.nb, 0, cfg, lut_cap,
+                                   P.id_bits, P.step, probes, P.nprobe(), P.nprobe() > 0, s, e0,
+                                   nullptr),
+                      "boundary step");
+            hip_check(launch_tb(grids + 6 + cur,
+                                reinterpret_cast<const TBSet *>(tab + GRID_TBSET_OFF), P.tbset.n,
+                                cfg, lut_cap, P.id_bits, P.step, s),
+                      "two-level step");
+            hip_check(launch_fused(grids + 2 * mid + (1 - pp), tset, 1, P.tiles.nb, 0, cfg,
+                                   lut_cap, P.id_bits, P.step + 1, probes, P.nprobe(),
+                                   P.nprobe() > 0, s, nullptr, e1),
+                      "boundary step");
+            P.parity = (cur + 2) % 3;
+            if (P.nprobe() > 0) P.sampled = std::max(P.sampled, P.step + 1);
+        } else if (fused) {
             // the launch samples its input level P.step (if >= 1) as well
-            const char *tab = P.base + P.r_grid.off;
-            LaunchCfg cfg = P.cfg;
-            cfg.order = tile_order(P.cfg, P.ws_bytes);
-            cfg.stream = stream_stores(P.cfg, P.ws_bytes);
-            hip_check(launch_fused(reinterpret_cast<const DevGrid<float> *>(tab) + P.parity,
-                                   reinterpret_cast<const TileSet *>(tab + GRID_SET_OFF), 1,
-                                   P.tiles.nb, P.tiles.ni, cfg,
-                                   std::max<int32_t>(1, (int32_t)(P.lut[0].size() / 4)),
-                                   P.id_bits, P.step,
-                                   reinterpret_cast<const DevProbes *>(
-                                       tab + (ring ? GRID_PROBES2_OFF : GRID_PROBES_OFF)),
+            hip_check(launch_fused(grids + 2 * P.parity + (int)(P.step & 1), tset, 1, P.tiles.nb,
+                                   P.tiles.ni, cfg, lut_cap, P.id_bits, P.step, probes,
                                    P.nprobe(), P.nprobe() > 0, s, e0, e1),
                       "fused step");
-            P.parity = 1 - P.parity;
+            P.parity = (P.parity + 1) % P.nbuf;
             if (P.nprobe() > 0 && P.step >= 1) P.sampled = std::max(P.sampled, P.step);
         } else if (P.g.precision == FDTD_FP64) {
             const DevGrid<double> d = P.dev_grid<double>();
@@ -772,10 +949,11 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s, double *ring = null
             hip_check(launch_probe(d, pr, P.step + 1, s), "probe");
             P.sampled = P.step + 1;
         }
-        P.step += 1;
-        // the ring holds K samples: fold them in before the next one would
-        // overwrite an unfolded slot
-        if (P.sampled - P.dft_n >= P.K - 1) flush_dft(P, s, ring);
+        P.step += adv;
+        t += adv;
+        // the ring holds K samples: fold them in before a later one would
+        // overwrite an unfolded slot (a pass samples at most two levels)
+        if (P.sampled - P.dft_n >= P.K - 2) flush_dft(P, s, ring);
     }
     if (fused && P.sampled < P.step) {
         // the last level of the run has not been sampled by a launch yet
@@ -1202,6 +1380,47 @@ fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, in
     if (!plan) return FDTD_E_INVALID_ARG;
     if (mode) *mode = plan->cfg.stream;
     if (used) *used = stream_stores(plan->cfg, plan->ws_bytes);
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_plan_set_temporal(fdtd_plan *plan, int32_t mode)
+{
+    PLAN_GUARD(plan) {
+        REQUIRE(mode >= -1 && mode <= 1, FDTD_E_INVALID_ARG, "two-level mode must be -1, 0 or 1");
+        REQUIRE(!plan->finalized, FDTD_E_STATE, "two-level mode is set before the plan is finalized");
+        REQUIRE(mode != 1 || plan->g.kernel == FDTD_KERNEL_FUSED, FDTD_E_UNSUPPORTED,
+                "two-level steps need the fused FP32 kernel");
+        plan->tb_mode = mode;
+    });
+}
+
+fdtd_status fdtd_plan_set_temporal_config(fdtd_plan *plan, int32_t tile_rows, int32_t zchunk)
+{
+    PLAN_GUARD(plan) {
+        REQUIRE(valid_tb_rows(tile_rows), FDTD_E_INVALID_ARG, "two-level tile rows must be 8, 10 or 13");
+        REQUIRE(zchunk >= 4 && zchunk <= 256, FDTD_E_INVALID_ARG,
+                "two-level z-chunk must be in [4, 256]");
+        plan->cfg.tb_rows = tile_rows;
+        plan->cfg.tb_zchunk = zchunk;
+    });
+}
+
+fdtd_status fdtd_plan_get_temporal(const fdtd_plan *plan, int32_t *mode, int32_t *used,
+                                   int32_t *tile_rows, int32_t *zchunk, int32_t *tiles)
+{
+    if (!plan) return FDTD_E_INVALID_ARG;
+    if (mode) *mode = plan->tb_mode;
+    if (used) *used = plan->tb ? 1 : 0;
+    if (tile_rows) *tile_rows = plan->cfg.tb_rows;
+    if (zchunk) *zchunk = plan->cfg.tb_zchunk;
+    if (tiles) {
+        if (!plan->tb) {
+            *tiles = 0;
+        } else {
+            TileSet t = make_tileset(*plan, plan->cfg);
+            *tiles = make_tbset(*plan, plan->cfg, t).n;
+        }
+    }
     return FDTD_OK;
 }
 
