@@ -372,6 +372,7 @@ def main():
     rows, zchunk = fd.fdtd_plan_get_config(sim.handle)
     order = fd.fdtd_plan_get_tile_order(sim.handle)
     sstores = fd.fdtd_plan_get_stream_stores(sim.handle)
+    tmode, tused, trows, tzc, ttiles = sim.temporal()
     sim.close()
     assert np.all(np.isfinite(V)) and res is not None
 
@@ -401,6 +402,8 @@ def main():
             "cells": cells, "timesteps_per_run": LINE_STEPS, "frequencies": len(prob.freqs),
             "layer_cells": layer_cells, "tile_rows": rows, "zchunk": zchunk,
             "tile_order": order[1], "stream_stores": sstores[1],
+            "two_level": {"used": bool(tused and ttiles > 0), "tiles": ttiles,
+                          "tile": [60, trows, tzc]},
         },
         "roofline": {
             "bound": "hbm",
@@ -415,9 +418,13 @@ def main():
             # cache, so this is not a DRAM fraction
             "counted_frac": (round(traffic / kavg_s / 1e9 / HBM_PEAK_GBS, 4)
                              if traffic else None),
-            "kernel": "k_fused<R, layers>: one leapfrog step = boundary-tile launch + "
-                      "interior-tile launch, timed together by HIP events on the run "
-                      "stream around windows of 16 consecutive steps",
+            "kernel": "one leapfrog step: with two-level steps a pair of steps is the "
+                      "boundary-tile launch k_fused<R, true>, the two-level launch k_tb "
+                      "over the interior tiles and k_fused<R, true> again, timed together "
+                      "by HIP events on the run stream around windows of 16 consecutive "
+                      "steps; achieved = the single-pass algorithmic bytes of a step over "
+                      "the step time (the effective rate: a two-level pass moves the "
+                      "interior's fields once for two steps)",
             "bytes_per_launch": bytes_step,
             "avg_launch_us": round(kavg_s * 1e6, 3),
             "launches": launches,
@@ -433,6 +440,19 @@ def main():
 
     if not args.no_variants:
         var = {}
+        # the same runs by single steps only: the fraction of the single-pass
+        # fused kernel
+        sim = fd.Simulation(prob, fused=True, temporal=0)
+        sim.run(10)
+        d1, k1, V1, I1 = timed_plan_run(fd, sim, LINE_STEPS)
+        sim.close()
+        var["line_fused_single_steps"] = {
+            "value": round(prob.ncells * LINE_STEPS / d1 / 1e6, 1), "unit": "Mcell-updates/s",
+            "timesteps": LINE_STEPS, "avg_step_us": round(k1 * 1e3, 2),
+            "bytes_per_step": bytes_step,
+            "hbm_frac": round(bytes_step / (k1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if g is not None:
+            var["line_fused_single_steps"]["spectra_vs_oracle"] = spectra_errors(V1, I1, g)
         for name, prec in (("line_fp64_plain", fd.FP64), ("line_fp32_plain", fd.FP32)):
             e, Vp, Ip = measure_plain(fd, prob, prec, LINE_STEPS)
             if g is not None:
