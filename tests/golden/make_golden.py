@@ -13,7 +13,9 @@ Case kinds:
     S-matrix the per-port protocol (Sec. II-A) forms from the pair;
   * the 1024x512x256 line after its first steps: port spectra and field
     values at stored positions (both port planes around the strip, and a
-    seeded sample of the whole grid).
+    seeded sample of the whole grid);
+  * the four runs of the step circuit's per-port protocol (the appendix's
+    pulse-width check): every run's spectra and the resulting S-matrix.
 
     python tests/golden/make_golden.py [name ...]
 """
@@ -54,10 +56,21 @@ CASES = {
     "smatrix_w4_ny100": lambda: _pair(4, False),
     # first 2000 steps of the 1024x512x256 layered lossy line
     "line_1024x512x256_2000": lambda: W.large_line(nsteps=2000),
+    # the paper's own verification microstrip (Sec. II-B), 60 000 steps
+    "paper_microstrip_1000x200x50": lambda: W.paper_microstrip(),
+    # the appendix's pulse-width check on the step circuit: the four runs of
+    # the per-port protocol driven by eq. 3 pulses of two widths, PEC strip
+    # (9000 steps) and 5.8e7 S/m strip (36 000 steps)
+    "step_pulse_pec_1p5fs": lambda: W.small_step_circuit(pulse_width=1.5e-15),
+    "step_pulse_pec_2p25fs": lambda: W.small_step_circuit(pulse_width=2.25e-15),
+    "step_pulse_lossy_1p5fs": lambda: W.small_step_circuit(pulse_width=1.5e-15, lossy=True),
+    "step_pulse_lossy_2p25fs": lambda: W.small_step_circuit(pulse_width=2.25e-15, lossy=True),
 }
 SPECTRA_ONLY = {"sweep_00_128x128x128", "sweep_15_320x160x96"}
 PAIRS = {"smatrix_w4_ny100_thz", "smatrix_w16_ny140_thz", "smatrix_w4_ny100"}
 FIELD_CASES = {"line_1024x512x256_2000"}
+PROTOCOLS = {"step_pulse_pec_1p5fs", "step_pulse_pec_2p25fs", "step_pulse_lossy_1p5fs",
+             "step_pulse_lossy_2p25fs"}
 
 
 def _c(z):
@@ -97,7 +110,21 @@ def make(name):
     made = CASES[name]()
     out = {"_about": f"FP64 CPU oracle results for {name} "
                      "(written by tests/golden/make_golden.py)."}
-    if name in PAIRS:
+    if name in PROTOCOLS:
+        spectra = {}
+        for key, p in made.items():
+            o = _run(name, p, t)
+            V, I = o.spectra()
+            spectra[key] = (V, I)
+            out[key] = {"name": p.name, "V": [_c(v) for v in V], "I": [_c(i) for i in I]}
+            out["dt"] = o.dt
+            del o
+        p1 = made["tot1"]
+        r = post.sparams(p1.freqs, *post.protocol_from_runs(spectra))
+        out.update({"nsteps": p1.nsteps, "freqs": p1.freqs.tolist(),
+                    "S_star": _c(r["S_star"]), "S": _c(r["S"]), "Zr": _c(r["Zr"]),
+                    "Z0": _c(r["Z0"]), "tau": r["tau"].tolist()})
+    elif name in PAIRS:
         p1, p2 = made
         runs = {}
         for key, p in (("p1", p1), ("p2", p2)):
@@ -129,7 +156,7 @@ def make(name):
             out.update({"S_star": _c(r["S_star"]), "S": _c(r["S"]), "Zr": _c(r["Zr"]),
                         "Z0": _c(r["Z0"]), "tau": r["tau"].tolist()})
     out["seconds"] = time.time() - t
-    out["threads"] = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out["threads"] = oracle.threads()
     tmp = os.path.join(HERE, f"{name}_oracle.json.tmp")
     with open(tmp, "w") as f:
         json.dump(out, f)

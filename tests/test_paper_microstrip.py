@@ -145,3 +145,32 @@ def test_delay_is_between_quasi_static_bounds(run):
     assert np.all(tau < length * np.sqrt(3.8) / C0)
     # weak dispersion in this band: the delay varies by a few percent
     assert np.ptp(tau) / np.mean(tau) < 0.03
+
+
+def test_run_matches_stored_oracle(run):
+    """The same 60 000-step run against the FP64 oracle's stored run of it
+    (tests/golden, written by the oracle alone): spectra of both ports, and
+    S*, S, Z0 and the delay over the whole frequency grid."""
+    import json
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "paper_microstrip_1000x200x50_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle run missing: {path} (tests/golden/make_golden.py)")
+    with open(path) as f:
+        g = json.load(f)
+    p, V, I, r = run
+    assert g["nsteps"] == p.nsteps and np.array_equal(p.freqs, g["freqs"])
+    c = lambda d: np.asarray(d["re"]) + 1j * np.asarray(d["im"])
+    Vo = np.array([c(x) for x in g["V"]])
+    Io = np.array([c(x) for x in g["I"]])
+    ev = np.max(np.abs(V - Vo)) / np.max(np.abs(Vo))
+    ei = np.max(np.abs(I - Io)) / np.max(np.abs(Io))
+    ds_star = np.max(np.abs(r["S_star"] - c(g["S_star"])))
+    ds = np.max(np.abs(r["S"] - c(g["S"])))
+    dz0 = np.max(np.abs(r["Z0"] / c(g["Z0"]) - 1))
+    tau_o = np.asarray(g["tau"])[:, 1, 0]
+    dtau = np.max(np.abs(r["tau"][:, 1, 0] / tau_o - 1))
+    print(f"paper microstrip vs oracle: spectra V {ev:.1e} I {ei:.1e}; |dS*| {ds_star:.1e} "
+          f"|dS| {ds:.1e} Z0 {dz0:.1e} tau {dtau:.1e}", flush=True)
+    assert ev < 1e-4 and ei < 1e-4
+    assert ds_star <= 1e-3 and ds <= 1e-3 and dz0 <= 5e-3 and dtau <= 5e-3

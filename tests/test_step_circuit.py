@@ -140,21 +140,74 @@ def test_sparams_do_not_depend_on_the_pulse_width(metal):
         assert np.max(np.abs(ra["S_star"][band, 1, 0])) < 0.999
 
 
-def _refined_step(scale):
-    s = scale
-    return W.step_circuit(nx=96 * s, ny=40 * s, nz=28 * s, delta=5e-9 / s, w1=4 * s, w2=8 * s,
-                          step_x=48 * s, sub_top=8 * s, strip_t=2 * s, pml=8 * s,
-                          src_margin=12 * s, port_margin=24 * s, nsteps=9000 * s, nf=16,
-                          fp32=True, z_step=1 * s)
+def _gold(name):
+    import json
+    path = os.path.join(os.path.dirname(__file__), "golden", name + "_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle run missing: {path} (tests/golden/make_golden.py)")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _c(d):
+    return np.asarray(d["re"]) + 1j * np.asarray(d["im"])
 
 
 @pytest.mark.gpu
-def test_sparams_converge_under_grid_refinement():
+@pytest.mark.parametrize("metal,width", [("pec", "1p5"), ("pec", "2p25"), ("lossy", "1p5"),
+                                         ("lossy", "2p25")])
+def test_pulse_width_runs_match_stored_oracle(metal, width):
+    """The oracle leg of the pulse-width check: each of its four-run batches
+    (eq. 3 pulse of sigma 1.5 or 2.25 fs; PEC strip over 9000 steps or the
+    5.8e7 S/m strip over 36 000) against the oracle's stored runs of the
+    same batch: every run's spectra, and S*, S, Z0 and the delay."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_04371_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2208_04371_amd as fd
+    g = _gold(f"step_pulse_{metal}_{width}fs")
+    runs = W.small_step_circuit(pulse_width={"1p5": 1.5e-15, "2p25": 2.25e-15}[width],
+                                lossy=metal == "lossy")
+    names = list(runs)
+    p = runs["tot1"]
+    assert g["nsteps"] == p.nsteps and np.array_equal(p.freqs, g["freqs"])
+    bs = fd.BatchSimulation([runs[n] for n in names])
+    bs.run(p.nsteps)
+    spectra = {n: bs.spectra(q) for q, n in enumerate(names)}
+    bs.close()
+    for n in names:
+        assert g[n]["name"] == runs[n].name
+        V, I = spectra[n]
+        Vo = np.array([_c(x) for x in g[n]["V"]])
+        Io = np.array([_c(x) for x in g[n]["I"]])
+        ev = np.max(np.abs(V - Vo)) / np.max(np.abs(Vo))
+        ei = np.max(np.abs(I - Io)) / np.max(np.abs(Io))
+        assert ev < 1e-4 and ei < 1e-4, (n, ev, ei)
+    r = fd.fdtd_sparams(p.freqs, *fd.protocol_from_runs(spectra))
+    ds_star = np.max(np.abs(r["S_star"] - _c(g["S_star"])))
+    ds = np.max(np.abs(r["S"] - _c(g["S"])))
+    dz0 = np.max(np.abs(r["Z0"] / _c(g["Z0"]) - 1))
+    gt = np.asarray(g["tau"])
+    dtau = np.max(np.abs(r["tau"][:, 1, 0] / gt[:, 1, 0] - 1))
+    print(f"{metal} {width} fs vs oracle: |dS*| {ds_star:.1e} |dS| {ds:.1e} Z0 {dz0:.1e} "
+          f"tau {dtau:.1e}", flush=True)
+    assert ds_star < 1e-3 and ds < 1e-3 and dz0 < 5e-3 and dtau < 5e-3
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("metal", ["pec", "lossy"])
+def test_sparams_converge_under_grid_refinement(metal):
     """The other half of the paper's convergence check: the same step circuit
     on cells of 5, 2.5 and 1.25 nm (every feature scaled with them; the
-    finest grid is 6.9 M cells over 36 000 steps) changes its S* less under
-    the second halving than under the first, and by less than 0.03.  (Sharp
-    metal edges make the convergence about first order.)"""
+    finest grid is 6.9 M cells) changes its S* less under the second halving
+    than under the first.  PEC strip: 9000 steps at 5 nm, S* changes by
+    0.046 then 0.021 (sharp metal edges make the convergence about first
+    order).  The paper's case, a thin lossy strip (5.8e7 S/m, a skin depth of
+    about 5 nm at 150 THz, so the finer grids resolve it): 36 000 steps at
+    5 nm."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -164,7 +217,7 @@ def test_sparams_converge_under_grid_refinement():
     import paper_2208_04371_amd as fd
     S = {}
     for scale in (1, 2, 4):
-        runs = _refined_step(scale)
+        runs = W.small_step_circuit(lossy=metal == "lossy", scale=scale)
         names = list(runs)
         print(f"refinement {scale}: {runs['tot1'].nx}x{runs['tot1'].ny}x{runs['tot1'].nz}",
               flush=True)
@@ -176,6 +229,6 @@ def test_sparams_converge_under_grid_refinement():
         S[scale] = fd.fdtd_sparams(p.freqs, *fd.protocol_from_runs(spectra))["S_star"]
     d1 = np.max(np.abs(S[1] - S[2]))
     d2 = np.max(np.abs(S[2] - S[4]))
-    print(f"max |dS*|: 5 -> 2.5 nm {d1:.4f}, 2.5 -> 1.25 nm {d2:.4f}", flush=True)
+    print(f"{metal}: max |dS*|: 5 -> 2.5 nm {d1:.4f}, 2.5 -> 1.25 nm {d2:.4f}", flush=True)
     assert d2 < 0.6 * d1
     assert d2 < 0.03

@@ -369,6 +369,30 @@ def step_circuit(nx=400, ny=120, nz=80, delta=5e-9, w1=8, w2=16, step_x=200, sub
             "inc2": prob("inc2", "uniform2", src2), "tot2": prob("tot2", "step", src2)}
 
 
+def small_step_circuit(fp32: bool = True, pulse_width: Optional[float] = None,
+                       lossy: bool = False, scale: int = 1) -> dict:
+    """The 96x40x28 step circuit of the convergence checks (5 nm cells: a
+    4-cell strip on an 8-cell silicon substrate that widens to 8 cells and
+    rises by one cell halfway; 8-cell absorbing layers; 16 frequencies over
+    10-300 THz; 9000 steps), as the four runs of the per-port protocol.
+    ``pulse_width``: excite with eq. 3's differential Gaussian of that sigma
+    (seconds) instead of the Gaussian-modulated sine; ``lossy``: the strip is
+    a 5.8e7 S/m metal instead of PEC and the runs last 36 000 steps (the
+    lossy line rings down slowly); ``scale``: cells ``scale`` times finer,
+    every feature and the step count scaled with them."""
+    s = scale
+    runs = step_circuit(nx=96 * s, ny=40 * s, nz=28 * s, delta=5e-9 / s, w1=4 * s, w2=8 * s,
+                        step_x=48 * s, sub_top=8 * s, strip_t=2 * s, pml=8 * s,
+                        src_margin=12 * s, port_margin=24 * s,
+                        nsteps=(36000 if lossy else 9000) * s, nf=16, fp32=fp32, z_step=1 * s)
+    for p in runs.values():
+        if pulse_width is not None:
+            p.source = Source(DIFF_GAUSSIAN, p.source.box, width=pulse_width)
+        if lossy:
+            p.materials[2] = Material(1.0, sigma=5.8e7)
+    return runs
+
+
 def window(p: Problem, box: Tuple[int, int, int, int, int, int], name: str = "") -> Problem:
     """The cells [x0, x1) x [y0, y1) x [z0, z1) of ``p`` as a problem of
     their own, for light-cone checks: faces that are faces of ``p`` keep their
