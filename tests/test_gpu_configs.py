@@ -155,3 +155,40 @@ def test_line_first_2000_steps_match_stored_oracle(fd, kernel):
     _say(f"  spectra V {ev:.1e} I {ei:.1e}; fields E {errs[0]:.1e} H {errs[1]:.1e}")
     tol = 1e-10 if kernel == "fp64" else 1e-4
     assert ev < tol and ei < tol and max(errs) < tol
+
+
+def test_line_long_run_fused_matches_plain_fp64(fd):
+    """The second link of the parity chain on the 1024x512x256 line: the
+    fused FP32 run (two-level steps, the benchmark's launch shape) against
+    the plain FP64 kernels, which the first link ties to the oracle, over
+    20 000 steps (the pulse has crossed the line; 2.7e12 cell updates):
+    port spectra, and S*, Z0 and delay where both ports' spectra are within
+    20 dB of their peaks."""
+    p = W.large_line(nsteps=20000)
+    out = {}
+    for kernel in ("fused", "fp64"):
+        _say(f"line {p.nx}x{p.ny}x{p.nz}, {kernel}, {p.nsteps} steps")
+        if kernel == "fused":
+            sim = fd.Simulation(p, fused=True)
+            _say(f"  two-level {sim.temporal()}")
+        else:
+            sim = fd.Simulation(p, fused=False, precision=fd.FP64)
+        sim.run()
+        out[kernel] = sim.spectra()
+        sim.close()
+    (Vf, If), (Vd, Id) = out["fused"], out["fp64"]
+    ev, ei = _rel(Vf, Vd), _rel(If, Id)
+    rf = pair_sparams(fd, p.freqs, (Vf, If), (Vf[::-1], If[::-1]))
+    rd = pair_sparams(fd, p.freqs, (Vd, Id), (Vd[::-1], Id[::-1]))
+    strong = np.ones(len(p.freqs), bool)
+    for q in range(2):
+        a = np.abs(Vd[q])
+        strong &= a > 0.1 * a.max()
+    ds = float(np.max(np.abs(rf["S_star"][strong] - rd["S_star"][strong])))
+    dz0 = float(np.max(np.abs(rf["Z0"][strong] / rd["Z0"][strong] - 1)))
+    dtau = float(np.max(np.abs(rf["tau"][strong, 1, 0] / rd["tau"][strong, 1, 0] - 1)))
+    _say(f"  spectra V {ev:.1e} I {ei:.1e}; over {strong.sum()} frequencies |dS*| {ds:.1e} "
+         f"Z0 {dz0:.1e} tau {dtau:.1e}")
+    assert strong.sum() >= 8
+    assert ev < 1e-4 and ei < 1e-4
+    assert ds <= 1e-3 and dz0 <= 5e-3 and dtau <= 5e-3
