@@ -372,10 +372,9 @@ fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, in
  * other tiles take the two steps one at a time; the plan keeps a third field
  * buffer for the intermediate level of those tiles.  This halves the field
  * traffic of the interior tiles, which is what bounds the step on grids far
- * larger than the memory-side cache.  The update formulas, sampling and
- * results are those of single steps (FP32 rounding aside: the two kinds of
- * pass may contract products differently).  Runs of an odd number of steps
- * end with a single step.
+ * larger than the memory-side cache.  The update formulas, their rounding,
+ * the sampling and so the results are bitwise those of single steps.  Runs
+ * of an odd number of steps end with a single step.
  * set_temporal: mode 1 on, 0 off, -1 (default) automatic: on when the plan's
  * state with two buffers would exceed 512 MiB and its default launch shape
  * leaves two-level tiles.  Before the plan is finalized (STATE after);

@@ -100,6 +100,20 @@ __device__ __forceinline__ float4 lut_entry(const float *lut, int id)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The two update formulas with their rounding pinned (fused multiply-adds in
+// a fixed order), so that the single-level and the two-level kernels give the
+// same bits for the same inputs whatever the compiler contracts elsewhere:
+//   H' = (H - c1 d1) + c2 d2            (c = dt / (mu0 delta))
+//   E' = (Ca E + Cb1 d1) - Cb2 d2       (Cb1, Cb2 = Cb / delta of the two axes)
+__device__ __forceinline__ float h_upd(float h, float c1, float d1, float c2, float d2)
+{
+    return __builtin_fmaf(c2, d2, __builtin_fmaf(-c1, d1, h));
+}
+__device__ __forceinline__ float e_upd(float e, const float4 &c, float d1, float d2)
+{
+    return __builtin_fmaf(-c.z, d2, __builtin_fmaf(c.y, d1, c.x * e));
+}
+
 // Layer-modified difference: diff/kappa + psi with psi <- b psi + c diff
 // (b, c, 1/kappa of the position, from the block's LDS profile cache).
 __device__ __forceinline__ float lterm(float diff, float b, float c, float ik, float psi_old,
@@ -236,9 +250,9 @@ __device__ __forceinline__ void h_apply(const DevGrid<float> &d, const Tabs<X, Y
             if (store) stf(d.psi_o[PSI_HYZ], L.qz, pn);
         }
     }
-    ox = hx - d.ch[1] * df.ez_y + d.ch[2] * df.ey_z;
-    oy = hy - d.ch[2] * df.ex_z + d.ch[0] * df.ez_x;
-    oz = hz - d.ch[0] * df.ey_x + d.ch[1] * df.ex_y;
+    ox = h_upd(hx, d.ch[1], df.ez_y, d.ch[2], df.ey_z);
+    oy = h_upd(hy, d.ch[2], df.ex_z, d.ch[0], df.ez_x);
+    oz = h_upd(hz, d.ch[0], df.ey_x, d.ch[1], df.ex_y);
 }
 
 // The E^n patch of one plane: rows y0-1 .. y0+Y (Y+2) of the three
@@ -493,9 +507,9 @@ __device__ __forceinline__ void march_plane(const DevGrid<float> &d, Smem<X, Y> 
         const float4 cx = tb.coef(0, cur.ids & IDM);
         const float4 cy = tb.coef(1, (cur.ids >> IDB) & IDM);
         const float4 cz = tb.coef(2, (cur.ids >> (2 * IDB)) & IDM);
-        const float ex = cx.x * sm.e[s0][0][ly][lx] + cx.y * dHz_y - cx.z * dHy_z;
-        const float ey = cy.x * sm.e[s0][1][ly][lx] + cy.y * dHx_z - cy.z * dHz_x;
-        float ez = cz.x * sm.e[s0][2][ly][lx] + cz.y * dHy_x - cz.z * dHx_y;
+        const float ex = e_upd(sm.e[s0][0][ly][lx], cx, dHz_y, dHy_z);
+        const float ey = e_upd(sm.e[s0][1][ly][lx], cy, dHx_z, dHz_x);
+        float ez = e_upd(sm.e[s0][2][ly][lx], cz, dHy_x, dHx_y);
         if (t.src_col && k >= d.src_box[4] && k <= d.src_box[5]) ez += t.sval;
         field_st<NT>(d.Eo[0], c, ex);
         field_st<NT>(d.Eo[1], c, ey);
@@ -815,8 +829,8 @@ hipError_t launch_class(const DevGrid<float> *g, const TileSet *sets, int ninst,
 //   E^{n+2}:    x0   .. x0+59, y0   .. y0+R-1    lanes 2..61, waves 2..R+1
 // E^n is needed on x0-2 .. x0+61, y0-2 .. y0+R+1: each thread loads its own
 // column, the first three waves the extra row y0+R+1 (one component each).
-// Update formulas and their operation order are those of the single-level
-// kernel (h_apply and the E update of march_plane).
+// Update formulas and their rounding are those of the single-level kernel
+// (h_upd, e_upd): a two-level pass gives the bits of two single steps.
 template <int R>
 struct TBSmem {
     // Only the y neighbours go through LDS (x neighbours are lanes of the
@@ -940,9 +954,9 @@ __device__ __forceinline__ void tb_plane(const TBPtr &d, TBSmem<R> &sm, const fl
     // ---- H^{n+1/2}(m) ------------------------------------------------------
     const float ex = st.e0[0], ey = st.e0[1], ez = st.e0[2];
     const float ezx = lane_next(ez), eyx = lane_next(ey);
-    const float h1x = cur.h[0] - d.ch[1] * (sm.e0[q][1][w + 1][lane] - ez) + d.ch[2] * (cur.e[1] - ey);
-    const float h1y = cur.h[1] - d.ch[2] * (cur.e[0] - ex) + d.ch[0] * (ezx - ez);
-    const float h1z = cur.h[2] - d.ch[0] * (eyx - ey) + d.ch[1] * (sm.e0[q][0][w + 1][lane] - ex);
+    const float h1x = h_upd(cur.h[0], d.ch[1], sm.e0[q][1][w + 1][lane] - ez, d.ch[2], cur.e[1] - ey);
+    const float h1y = h_upd(cur.h[1], d.ch[2], cur.e[0] - ex, d.ch[0], ezx - ez);
+    const float h1z = h_upd(cur.h[2], d.ch[0], eyx - ey, d.ch[1], sm.e0[q][0][w + 1][lane] - ex);
     sm.h1[0][w][lane] = h1x;
     sm.h1[1][w][lane] = h1z;
     lds_barrier();
@@ -961,9 +975,9 @@ __device__ __forceinline__ void tb_plane(const TBPtr &d, TBSmem<R> &sm, const fl
         const float4 cx = lut[cur.id & IDM];
         const float4 cy = lut[cap + ((cur.id >> IDB) & IDM)];
         const float4 cz = lut[2 * cap + ((cur.id >> (2 * IDB)) & IDM)];
-        e1x = cx.x * ex + cx.y * dHz_y - cx.z * dHy_z;
-        e1y = cy.x * ey + cy.y * dHx_z - cy.z * dHz_x;
-        e1z = cz.x * ez + cz.y * dHy_x - cz.z * dHx_y;
+        e1x = e_upd(ex, cx, dHz_y, dHy_z);
+        e1y = e_upd(ey, cy, dHx_z, dHz_x);
+        e1z = e_upd(ez, cz, dHy_x, dHx_y);
         // (sval1 is zero off the source columns)
         if (m >= t.sk0 && m <= t.sk1) e1z += t.sval1;
     }
@@ -992,9 +1006,9 @@ __device__ __forceinline__ void tb_plane(const TBPtr &d, TBSmem<R> &sm, const fl
     // tangential E edges of the ground face)
     const bool below = m == 0;
     const float e1pzx = lane_next(st.e1p[2]), e1pyx = lane_next(st.e1p[1]);
-    float h2x = st.h1p[0] - d.ch[1] * (sm.e1[q][1][yp][lane] - st.e1p[2]) + d.ch[2] * (e1y - st.e1p[1]);
-    float h2y = st.h1p[1] - d.ch[2] * (e1x - st.e1p[0]) + d.ch[0] * (e1pzx - st.e1p[2]);
-    float h2z = st.h1p[2] - d.ch[0] * (e1pyx - st.e1p[1]) + d.ch[1] * (sm.e1[q][0][yp][lane] - st.e1p[0]);
+    float h2x = h_upd(st.h1p[0], d.ch[1], sm.e1[q][1][yp][lane] - st.e1p[2], d.ch[2], e1y - st.e1p[1]);
+    float h2y = h_upd(st.h1p[1], d.ch[2], e1x - st.e1p[0], d.ch[0], e1pzx - st.e1p[2]);
+    float h2z = h_upd(st.h1p[2], d.ch[0], e1pyx - st.e1p[1], d.ch[1], sm.e1[q][0][yp][lane] - st.e1p[0]);
     h2x = below ? 0.f : h2x;
     h2y = below ? 0.f : h2y;
     h2z = below ? 0.f : h2z;
@@ -1019,9 +1033,9 @@ __device__ __forceinline__ void tb_plane(const TBPtr &d, TBSmem<R> &sm, const fl
         const float4 cx = lut[st.idp & IDM];
         const float4 cy = lut[cap + ((st.idp >> IDB) & IDM)];
         const float4 cz = lut[2 * cap + ((st.idp >> (2 * IDB)) & IDM)];
-        const float e2x = cx.x * st.e1p[0] + cx.y * dHz_y - cx.z * dHy_z;
-        const float e2y = cy.x * st.e1p[1] + cy.y * dHx_z - cy.z * dHz_x;
-        float e2z = cz.x * st.e1p[2] + cz.y * dHy_x - cz.z * dHx_y;
+        const float e2x = e_upd(st.e1p[0], cx, dHz_y, dHy_z);
+        const float e2y = e_upd(st.e1p[1], cy, dHx_z, dHz_x);
+        float e2z = e_upd(st.e1p[2], cz, dHy_x, dHx_y);
         if (m - 1 >= t.sk0 && m - 1 <= t.sk1) e2z += t.sval2;
         field_st<NT>(d.Eo, co, e2x);
         field_st<NT>(comp_out(d.Eo, d.cstride, 1), co, e2y);
@@ -1145,8 +1159,8 @@ k_tb(const DevGrid<float> *__restrict__ grid, const TBSet *__restrict__ set, int
         const float ex = ldf(d.E[0], c), ey = ldf(d.E[1], c), ez = ldf(d.E[2], c);
         const float ezy = ldf(d.E[2], c + (uint32_t)d.px), ezx = ldf(d.E[2], c + 1u);
         const float hx = ldf(d.H[0], c), hy = ldf(d.H[1], c);
-        st.h1p[0] = hx - d.ch[1] * (ezy - ez) + d.ch[2] * (p0.e[1] - ey);
-        st.h1p[1] = hy - d.ch[2] * (p0.e[0] - ex) + d.ch[0] * (ezx - ez);
+        st.h1p[0] = h_upd(hx, g.ch[1], ezy - ez, g.ch[2], p0.e[1] - ey);
+        st.h1p[1] = h_upd(hy, g.ch[2], p0.e[0] - ex, g.ch[0], ezx - ez);
     }
     st.e0[0] = p0.e[0];
     st.e0[1] = p0.e[1];
