@@ -308,3 +308,63 @@ def test_coefficient_set_limits(fd):
         h = describe(p, fused=True)
         fdtd_plan_workspace_size(h)
     assert e.value.code == -3
+
+
+def test_two_level_mode_and_shape_arguments(fd):
+    """Two-level steps: the mode is set before the plan is finalized (STATE
+    after), the tile shape is checked, PLAIN plans refuse mode 1, automatic
+    mode leaves small plans at two buffers and turns the third on for the
+    1024x512x256 line (its state with two buffers is 7.6 GB), and a plan
+    with two-level steps cannot join a batch.  Host-only calls."""
+    from paper_2208_04371_amd import (describe, fdtd_plan_destroy, fdtd_plan_get_temporal,
+                                      fdtd_plan_set_temporal, fdtd_plan_set_temporal_config,
+                                      fdtd_plan_workspace_size)
+    p = W.small_microstrip()
+    h = describe(p, fused=True)
+    try:
+        assert fdtd_plan_get_temporal(h)[:4] == (-1, 0, 13, 16)
+        for bad in (-2, 2):
+            with pytest.raises(fd.FdtdError) as e:
+                fdtd_plan_set_temporal(h, bad)
+            assert e.value.code == -1
+        for rows, z in ((5, 16), (12, 16), (13, 3), (13, 257)):
+            with pytest.raises(fd.FdtdError) as e:
+                fdtd_plan_set_temporal_config(h, rows, z)
+            assert e.value.code == -1
+        fdtd_plan_set_temporal_config(h, 8, 32)
+        two = fdtd_plan_workspace_size(h)          # automatic: a 9 MB state stays at two
+        assert fdtd_plan_get_temporal(h)[:4] == (-1, 0, 8, 32)
+        with pytest.raises(fd.FdtdError) as e:
+            fdtd_plan_set_temporal(h, 1)
+        assert e.value.code == -2
+    finally:
+        fdtd_plan_destroy(h)
+    h = describe(p, fused=True)
+    try:
+        fdtd_plan_set_temporal(h, 1)
+        three = fdtd_plan_workspace_size(h)
+        assert fdtd_plan_get_temporal(h)[1] == 1
+        assert three > two                         # the third field buffer
+        with pytest.raises(fd.FdtdError) as e:
+            arr = (C.c_void_p * 1)(h.value)
+            out = C.c_void_p()
+            fd._capi.check(fd.lib().fdtd_batch_create(arr, 1, C.byref(out)), "fdtd_batch_create",
+                           None, batch=True)
+        assert e.value.code == -3
+    finally:
+        fdtd_plan_destroy(h)
+    hp = describe(p, fused=False)
+    try:
+        with pytest.raises(fd.FdtdError) as e:
+            fdtd_plan_set_temporal(hp, 1)
+        assert e.value.code == -3
+    finally:
+        fdtd_plan_destroy(hp)
+    # automatic mode on the 1024x512x256 line: three buffers, two-level tiles
+    hl = describe(W.large_line(nsteps=2), fused=True)
+    try:
+        fdtd_plan_workspace_size(hl)
+        mode, used, rows, z, tiles = fdtd_plan_get_temporal(hl)
+        assert mode == -1 and used == 1 and tiles > 0
+    finally:
+        fdtd_plan_destroy(hl)

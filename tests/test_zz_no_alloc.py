@@ -30,12 +30,12 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _both(fd, p, fused, precision, chunks):
+def _both(fd, p, fused, precision, chunks, temporal=None):
     """The problem run by fdtd_run and, on a second plan, by
     fdtd_run_noalloc in the given step chunks; fields and spectra of each."""
     out = []
     for noalloc in (False, True):
-        sim = fd.Simulation(p, fused=fused, precision=precision)
+        sim = fd.Simulation(p, fused=fused, precision=precision, temporal=temporal)
         for n in chunks:
             if noalloc:
                 fd.fdtd_run_noalloc(sim.handle, n)
@@ -73,6 +73,16 @@ def test_noalloc_resumed_equals_one_run(fd):
     _say("noalloc resumed, fused, 300 steps")
     a, _ = _both(fd, p, True, fd.FP32, [300])
     _, b = _both(fd, p, True, fd.FP32, [130, 170])
+    _assert_same(a, b)
+
+
+def test_noalloc_two_level_steps(fd):
+    """A plan with two-level steps (its source and ports inside the
+    two-level box), 101 steps in calls of 50 and 51."""
+    p = W.small_microstrip(nx=256, ny=64, nz=48, strip_w=8, sub_top=12, pml=6, src_i=80,
+                           ports=(100, 180), nsteps=101, nf=16, seed=7)
+    _say("noalloc vs run, two-level steps, 101 steps")
+    a, b = _both(fd, p, True, fd.FP32, [50, 51], temporal=1)
     _assert_same(a, b)
 
 
