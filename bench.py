@@ -453,6 +453,28 @@ def main():
             "hbm_frac": round(bytes_step / (k1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         if g is not None:
             var["line_fused_single_steps"]["spectra_vs_oracle"] = spectra_errors(V1, I1, g)
+        # launch shape and temporal-block depth chosen by the autotuner
+        # (first stage: rows x z-chunk x order; second: two-level tile
+        # shapes and single steps)
+        sim = fd.Simulation(prob, fused=True)
+        t_tune = time.perf_counter()
+        best = sim.autotune(trial_steps=16)
+        t_tune = time.perf_counter() - t_tune
+        da, ka, Va, Ia = timed_plan_run(fd, sim, LINE_STEPS)
+        ar, az = fd.fdtd_plan_get_config(sim.handle)
+        ao = fd.fdtd_plan_get_tile_order(sim.handle)
+        _, aused, atr, atz, atiles = sim.temporal()
+        sim.close()
+        var["line_autotuned"] = {
+            "value": round(prob.ncells * LINE_STEPS / da / 1e6, 1), "unit": "Mcell-updates/s",
+            "timesteps": LINE_STEPS, "avg_step_us": round(ka * 1e3, 2),
+            "hbm_frac": round(bytes_step / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "choice": {"index": best, "tile_rows": ar, "zchunk": az, "tile_order": ao[1],
+                       "two_level": {"used": bool(aused and atiles > 0), "tiles": atiles,
+                                     "tile": [60, atr, atz]}},
+            "search_s": round(t_tune, 2)}
+        if g is not None:
+            var["line_autotuned"]["spectra_vs_oracle"] = spectra_errors(Va, Ia, g)
         for name, prec in (("line_fp64_plain", fd.FP64), ("line_fp32_plain", fd.FP32)):
             e, Vp, Ip = measure_plain(fd, prob, prec, LINE_STEPS)
             if g is not None:

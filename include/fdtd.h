@@ -382,11 +382,13 @@ fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, in
  * Such plans cannot join a batch.
  * set_temporal_config: the two-level tiles are 60 cells in x, tile_rows
  * (8, 10 or 13) in y and zchunk (4..256) planes in z; default 13 x 16.
+ * It also makes the plan take two-level passes again where the autotuner
+ * chose single steps (depth 1, fdtd_plan_autotune).
  * INVALID_ARG for other values.  Takes effect at the next run.
- * get_temporal: the mode, whether the plan was finalized with the third
- * buffer (*used), the tile shape and the number of two-level tiles of the
- * current launch shape (0 if none; then every step is single).  Any output
- * may be NULL. */
+ * get_temporal: the mode, whether the plan takes two-level passes (*used:
+ * finalized with the third buffer, depth 2), the tile shape and the number
+ * of two-level tiles of the current launch shape (0 if none or if *used is
+ * 0; then every step is single).  Any output may be NULL. */
 fdtd_status fdtd_plan_set_temporal(fdtd_plan *plan, int32_t mode);
 fdtd_status fdtd_plan_set_temporal_config(fdtd_plan *plan, int32_t tile_rows, int32_t zchunk);
 fdtd_status fdtd_plan_get_temporal(const fdtd_plan *plan, int32_t *mode, int32_t *used,
@@ -394,7 +396,16 @@ fdtd_status fdtd_plan_get_temporal(const fdtd_plan *plan, int32_t *mode, int32_t
 
 /* fdtd_batch_autotune for one bound FUSED plan that is not in a batch: the
  * same candidates, timing and cache (a plan and a one-member batch of the
- * same grid shape share a cache entry).  The plan is reset afterwards unless
+ * same grid shape share a cache entry).  A plan finalized with two-level
+ * steps (fdtd_plan_set_temporal) is also tuned in its temporal-block depth:
+ * a second stage keeps the winning (rows, z-chunk, order) and times
+ * two-level passes with tiles of 8, 10 or 13 rows and z-chunks of 8, 16, 32
+ * or 64 planes (12 candidates, in that lexicographic order), then single
+ * steps only (depth 1); *best_index = i1 + 50 * i2 with i1 the first stage's
+ * index and i2 < 13 the second's.  Such plans have cache entries of their
+ * own, which also hold the depth and the two-level tile shape.  Any choice
+ * gives the same results bit for bit.
+ * The plan is reset afterwards unless
  * the shape came from the cache.  STATE if unbound or in a batch,
  * UNSUPPORTED for the plain kernels, INVALID_ARG for trial_steps < 1.  On a
  * failure the launch shape is the last one tried and the state is undefined

@@ -88,6 +88,8 @@ struct LaunchCfg {
     int32_t zchunk = 32;     // planes marched per block
     int32_t tb_rows = 13;    // two-level kernel: tile rows (8, 10 or 13)
     int32_t tb_zchunk = 16;  // two-level kernel: planes marched per block (4..256)
+    int32_t tb_depth = 2;    // levels per pass of the two-level tiles of a plan
+                             // with the third buffer: 2, or 1 (single steps)
     int32_t order = -1;      // block-to-tile order (see tile_order), -1 = automatic
     int32_t stream = -1;     // streaming field stores (see stream_stores), -1 = automatic
 };
@@ -359,6 +361,8 @@ LaunchCfg default_launch(const Plan *const *plans, size_t n);
 struct TuneHooks {
     std::function<void(const LaunchCfg &)> apply;
     std::function<void(int32_t)> run;
+    bool two_level = false;  // a plan with the third buffer: also search the
+                             // depth and tile shape of its two-level passes
 };
 // GPU architecture name of the current device (the cache key's first part).
 std::string tune_device_name();
@@ -366,8 +370,11 @@ std::string tune_device_name();
 std::string tune_shape_key(const Plan *const *plans, size_t n);
 // Times every candidate shape for trial_steps steps after one warm-up step
 // and applies the fastest; with cache_path, a stored shape for key is applied
-// instead (best_index = -1) and a timed winner is stored.  best_index is the
-// winner's position in (rows, z-chunk, order) lexicographic candidate order.
+// instead (best_index = -1) and a timed winner is stored.  The first stage
+// searches (rows, z-chunk, order) in lexicographic order (index i1 < 50);
+// with two_level, a second stage keeps that winner and searches two-level
+// passes over (tile rows, z-chunk) in lexicographic order, then single
+// steps (index i2 < 13).  best_index = i1 (+ 50 * i2 with two_level).
 hipError_t tune_search(const TuneHooks &h, int32_t trial_steps, const char *cache_path,
                        const std::string &key, hipStream_t s, LaunchCfg &best_cfg, int32_t &best_index);
 

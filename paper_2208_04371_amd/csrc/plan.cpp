@@ -906,7 +906,7 @@ static void run_plan(Plan &P, int64_t nsteps, hipStream_t s, double *ring = null
     cfg.stream = stream_stores(P.cfg, P.ws_bytes);
     for (int64_t t = 0; t < nsteps;) {
         // two levels per pass where the plan has two-level tiles
-        const bool pair = fused && P.tb && P.tbset.n > 0 && nsteps - t >= 2;
+        const bool pair = fused && P.tb && P.cfg.tb_depth == 2 && P.tbset.n > 0 && nsteps - t >= 2;
         const int adv = pair ? 2 : 1;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (!ring) hip_check(P.timer.step(e0, e1, t == 0, t + adv >= nsteps, adv), "timer");
@@ -1402,6 +1402,7 @@ fdtd_status fdtd_plan_set_temporal_config(fdtd_plan *plan, int32_t tile_rows, in
                 "two-level z-chunk must be in [4, 256]");
         plan->cfg.tb_rows = tile_rows;
         plan->cfg.tb_zchunk = zchunk;
+        plan->cfg.tb_depth = 2;
     });
 }
 
@@ -1410,11 +1411,12 @@ fdtd_status fdtd_plan_get_temporal(const fdtd_plan *plan, int32_t *mode, int32_t
 {
     if (!plan) return FDTD_E_INVALID_ARG;
     if (mode) *mode = plan->tb_mode;
-    if (used) *used = plan->tb ? 1 : 0;
+    const bool on = plan->tb && plan->cfg.tb_depth == 2;
+    if (used) *used = on ? 1 : 0;
     if (tile_rows) *tile_rows = plan->cfg.tb_rows;
     if (zchunk) *zchunk = plan->cfg.tb_zchunk;
     if (tiles) {
-        if (!plan->tb) {
+        if (!on) {
             *tiles = 0;
         } else {
             TileSet t = make_tileset(*plan, plan->cfg);
@@ -1436,11 +1438,14 @@ fdtd_status fdtd_plan_autotune(fdtd_plan *plan, int32_t trial_steps, const char 
         REQUIRE(trial_steps >= 1, FDTD_E_INVALID_ARG, "trial_steps must be >= 1");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const Plan *self = &P;
-        const std::string key = tune_device_name() + "|" + tune_shape_key(&self, 1);
+        // plans with the third buffer search more: their own cache entries
+        const std::string key = tune_device_name() + "|" + tune_shape_key(&self, 1) +
+                                (P.tb ? "two-level" : "");
         TimerPause pause(P.timer);   // trial launches are not the caller's
         TuneHooks h;
         h.apply = [&](const LaunchCfg &c) { P.cfg = c; };
         h.run = [&](int32_t n) { run_plan(P, n, s); };
+        h.two_level = P.tb;
         LaunchCfg best = P.cfg;
         int32_t best_i = -1;
         hip_check(tune_search(h, trial_steps, cache_path, key, s, best, best_i), "autotune");

@@ -17,18 +17,24 @@ namespace fdtd {
 namespace {
 
 // Candidates: tile rows x z-chunk x tile order (automatic, which follows
-// each launch's state size, or runs of 16).
+// each launch's state size, or runs of 16); for plans with two-level steps
+// then the two-level tile rows x z-chunk, and single steps.
 const int TUNE_ROWS[] = {2, 4, 8, 12, 16};
 const int TUNE_Z[] = {4, 8, 16, 32, 64};
 const int TUNE_ORDER[] = {-1, 16};
+const int TUNE_TB_ROWS[] = {8, 10, 13};
+const int TUNE_TB_Z[] = {8, 16, 32, 64};
+constexpr int TUNE_STAGE1 = 5 * 5 * 2;
 
 // The cache is a JSON object written one entry per line:
 //   {
-//   "gfx950:...|400x120x80;": [4, 32, 0.0312, 0],
+//   "gfx950:...|400x120x80;": [4, 32, 0.0312, 0, 2, 13, 16],
 //   ...
 //   }
-// (rows, z-chunk, milliseconds per step, tile order; an entry without the
-// order leaves it automatic).  Unknown lines are ignored.
+// (rows, z-chunk, milliseconds per step, tile order, two-level depth, tile
+// rows and z-chunk; an entry without the order leaves it automatic, one
+// without the last three leaves the two-level defaults).  Unknown lines are
+// ignored.
 std::vector<std::pair<std::string, std::string>> cache_read(const char *path)
 {
     std::vector<std::pair<std::string, std::string>> out;
@@ -52,13 +58,18 @@ bool cache_lookup(const char *path, const std::string &key, LaunchCfg &cfg)
 {
     for (const auto &e : cache_read(path)) {
         if (e.first != key) continue;
-        int rows = 0, z = 0, order = -1;
+        int rows = 0, z = 0, order = -1, depth = 2, tbr = 13, tbz = 16;
         double ms = 0;
-        if (std::sscanf(e.second.c_str(), "%d , %d , %lf , %d", &rows, &z, &ms, &order) >= 2 &&
-            valid_rows(rows) && z >= 1 && z <= 64 && valid_order(order)) {
+        const int n = std::sscanf(e.second.c_str(), "%d , %d , %lf , %d , %d , %d , %d", &rows, &z,
+                                  &ms, &order, &depth, &tbr, &tbz);
+        if (n >= 2 && valid_rows(rows) && z >= 1 && z <= 64 && valid_order(order) &&
+            (depth == 1 || depth == 2) && valid_tb_rows(tbr) && tbz >= 4 && tbz <= 256) {
             cfg.rows = rows;
             cfg.zchunk = z;
             cfg.order = order;
+            cfg.tb_depth = depth;
+            cfg.tb_rows = tbr;
+            cfg.tb_zchunk = tbz;
             return true;
         }
         return false;
@@ -70,7 +81,8 @@ void cache_store(const char *path, const std::string &key, const LaunchCfg &cfg,
 {
     auto entries = cache_read(path);
     char val[128];
-    std::snprintf(val, sizeof val, "%d, %d, %.6g, %d", cfg.rows, cfg.zchunk, ms, cfg.order);
+    std::snprintf(val, sizeof val, "%d, %d, %.6g, %d, %d, %d, %d", cfg.rows, cfg.zchunk, ms,
+                  cfg.order, cfg.tb_depth, cfg.tb_rows, cfg.tb_zchunk);
     bool found = false;
     for (auto &e : entries)
         if (e.first == key) { e.second = val; found = true; }
@@ -138,27 +150,61 @@ hipError_t tune_search(const TuneHooks &h, int32_t trial_steps, const char *cach
     EventPair ev;
     hipError_t e = ev.create();
     if (e != hipSuccess) return e;
+    // time one candidate: its milliseconds for trial_steps steps
+    auto time_one = [&](const LaunchCfg &c, float &ms) -> hipError_t {
+        h.apply(c);
+        h.run(1);   // warm-up
+        hipError_t r;
+        if ((r = hipEventRecord(ev.a, s)) != hipSuccess) return r;
+        h.run(trial_steps);
+        if ((r = hipEventRecord(ev.b, s)) != hipSuccess) return r;
+        if ((r = hipEventSynchronize(ev.b)) != hipSuccess) return r;
+        return hipEventElapsedTime(&ms, ev.a, ev.b);
+    };
     float best = 1e30f;
     int idx = 0;
     best_index = -1;
     for (int r : TUNE_ROWS)
         for (int z : TUNE_Z)
-        for (int o : TUNE_ORDER) {
-            LaunchCfg c;
-            c.rows = r;
-            c.zchunk = z;
-            c.order = o;
-            h.apply(c);
-            h.run(1);   // warm-up
-            if ((e = hipEventRecord(ev.a, s)) != hipSuccess) return e;
-            h.run(trial_steps);
-            if ((e = hipEventRecord(ev.b, s)) != hipSuccess) return e;
-            if ((e = hipEventSynchronize(ev.b)) != hipSuccess) return e;
+            for (int o : TUNE_ORDER) {
+                LaunchCfg c;
+                c.rows = r;
+                c.zchunk = z;
+                c.order = o;
+                float ms = 0;
+                if ((e = time_one(c, ms)) != hipSuccess) return e;
+                if (ms < best) { best = ms; best_index = idx; best_cfg = c; }
+                ++idx;
+            }
+    if (h.two_level) {
+        // the winner's launch shape with each two-level tile shape, then
+        // with single steps; all timed afresh, so the stage compares like
+        // with like
+        const LaunchCfg base = best_cfg;
+        const int i1 = best_index;
+        float best2 = 1e30f;
+        int j = 0;
+        auto consider = [&](const LaunchCfg &c) -> hipError_t {
             float ms = 0;
-            if ((e = hipEventElapsedTime(&ms, ev.a, ev.b)) != hipSuccess) return e;
-            if (ms < best) { best = ms; best_index = idx; best_cfg = c; }
-            ++idx;
-        }
+            const hipError_t r = time_one(c, ms);
+            if (r != hipSuccess) return r;
+            if (ms < best2) { best2 = ms; best_index = i1 + TUNE_STAGE1 * j; best_cfg = c; }
+            ++j;
+            return hipSuccess;
+        };
+        for (int r : TUNE_TB_ROWS)
+            for (int z : TUNE_TB_Z) {
+                LaunchCfg c = base;
+                c.tb_depth = 2;
+                c.tb_rows = r;
+                c.tb_zchunk = z;
+                if ((e = consider(c)) != hipSuccess) return e;
+            }
+        LaunchCfg c = base;
+        c.tb_depth = 1;
+        if ((e = consider(c)) != hipSuccess) return e;
+        best = best2;
+    }
     h.apply(best_cfg);
     if (cache_path) cache_store(cache_path, key, best_cfg, best / trial_steps);
     return hipSuccess;

@@ -100,3 +100,59 @@ def test_plan_autotune_picks_caches_and_resets(fd, tmp_path):
     assert e.value.code == -3
     for x in (sim, ref, bs, plain):
         x.close()
+
+
+def _tb_grid(nsteps):
+    # the 256x64x48 microstrip whose interior box holds two-level tiles
+    return W.small_microstrip(nx=256, ny=64, nz=48, strip_w=8, sub_top=12, pml=6, src_i=80,
+                              ports=(100, 180), nsteps=nsteps, nf=16, seed=7)
+
+
+def test_plan_autotune_chooses_temporal_depth(fd, tmp_path):
+    """A plan with two-level steps: the search also times two-level tile
+    shapes and single steps (12 + 1 candidates after the first stage).
+    Whatever it picks, the run equals the plan run by single steps bit for
+    bit, and a second plan of the same shape takes the cached choice,
+    depth and two-level shape included."""
+    cache = str(tmp_path / "tune.json")
+    p = _tb_grid(151)
+    sim = fd.Simulation(p, fused=True, temporal=1)
+    sim.run(5)
+    best = sim.autotune(trial_steps=4, cache_path=cache)
+    rows, z = sim.get_config()
+    order = sim.tile_order()[0]
+    mode, used, tbr, tbz, tiles = sim.temporal()
+    i1, i2 = best % 50, best // 50
+    print(f"plan autotune picked {best}: rows {rows} z {z} order {order}; two-level "
+          f"used {used} ({tbr} x {tbz}, {tiles} tiles)", flush=True)
+    assert 0 <= best < 50 * 13 and sim.step == 0
+    assert best % 2 == (order == 16)
+    if i2 == 12:
+        assert used == 0 and tiles == 0          # single steps chosen
+    else:
+        assert used == 1 and (tbr, tbz) == ((8, 10, 13)[i2 // 4], (8, 16, 32, 64)[i2 % 4])
+    with open(cache) as f:
+        entries = json.load(f)
+    (key, val), = entries.items()
+    assert key.endswith("|256x64x48;two-level")
+    assert val[:2] == [rows, z] and val[3] == order
+    assert val[4] == (1 if i2 == 12 else 2) and val[5:] == [tbr, tbz]
+    sim.run()
+    ref = fd.Simulation(p, fused=True, temporal=0, config=(rows, z))
+    ref.set_tile_order(order)
+    ref.run()
+    for c in range(6):
+        assert np.array_equal(sim.field(c), ref.field(c)), c
+    Va, Ia = sim.spectra()
+    Vb, Ib = ref.spectra()
+    assert np.array_equal(Va, Vb) and np.array_equal(Ia, Ib)
+    # the cached choice, applied untimed
+    again = fd.Simulation(p, fused=True, temporal=1)
+    assert again.autotune(trial_steps=4, cache_path=cache) == -1
+    assert again.get_config() == (rows, z) and again.tile_order()[0] == order
+    assert again.temporal()[1:4] == (used, tbr, tbz)
+    # a tile shape set by the caller brings two-level passes back
+    fd.fdtd_plan_set_temporal_config(again.handle, 13, 16)
+    assert again.temporal()[1:4] == (1, 13, 16)
+    for x in (sim, ref, again):
+        x.close()
