@@ -256,6 +256,26 @@ def bench_batch(fd, W, torch):
     if acc:
         acc["reference"] = "FP64 CPU oracle runs of the same excitation pairs (tests/golden)"
         out["accuracy"] = acc
+    # the same batch in lockstep: one launch pair per step over all twelve
+    # members (one group), autotuned for that schedule
+    lk = fd.BatchSimulation(probs)
+    lk.set_group_bytes(0)
+    lpick = lk.autotune(trial_steps=16)
+    lrows, lzc = lk.get_config()
+    lk.set_timing(TIMING_EVERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lk.run(nsteps)
+    for q in range(len(probs)):
+        lk.spectra(q)
+    torch.cuda.synchronize()
+    dl = time.perf_counter() - t0
+    lms, _ = lk.kernel_time()
+    lgroups = lk.groups()
+    lk.close()
+    out["lockstep"] = {"value": round(cells * nsteps / dl / 1e6, 1), "unit": "Mcell-updates/s",
+                       "groups": lgroups, "avg_step_us": round(lms / nsteps * 1e3, 2),
+                       "autotuned": {"candidate": lpick, "tile_rows": lrows, "zchunk": lzc}}
     solo = 0.0
     for p in probs:
         sim = fd.Simulation(p, fused=True)
