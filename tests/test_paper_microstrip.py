@@ -2,9 +2,11 @@
 a 25 ohm line (eps_r 3.8, w/h = 5.7, h = 1 mm on 0.1 mm cells), CFL 0.9,
 differential-Gaussian excitation (sigma = 11.254 ps), 60 000 steps.
 
-The run is far too long for the CPU oracle (6e11 cell updates), so it is
-checked through properties of a uniform line in the band where it carries a
-single quasi-TEM mode.  The strip is wide (5.7 mm): above ~10 GHz the line
+The run is 6e11 cell updates: the CPU oracle takes hours for it, so its
+stored run (tests/golden, written by tests/golden/make_golden.py) backs one
+test, element by element on the spectra and S-parameters.  The others check
+the physics of a uniform line in the band where it carries a single
+quasi-TEM mode.  The strip is wide (5.7 mm): above ~10 GHz the line
 disperses (the measured V/I impedance rises by ~10 % up to 19 GHz) and near
 20 GHz a higher-order mode sets in, so the checks stop below that:
   * the measured reference impedance (eq. 2) is the designed 25 ohm, within
