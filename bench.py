@@ -219,7 +219,10 @@ def bench_batch(fd, W, torch):
     probs = W.batched_smatrix(twin=True)
     nsteps = probs[0].nsteps
     bs = fd.BatchSimulation(probs)
-    pick = bs.autotune(trial_steps=16)     # outside the timed region; resets
+    # outside the timed region; resets.  64 trial steps: a grouped batch
+    # runs each group's trial in turn, and a group's first steps refill the
+    # memory-side cache
+    pick = bs.autotune(trial_steps=64)
     rows, zc = bs.get_config()
     order = bs.tile_order()
     bs.set_timing(TIMING_EVERY)
@@ -260,7 +263,7 @@ def bench_batch(fd, W, torch):
     # members (one group), autotuned for that schedule
     lk = fd.BatchSimulation(probs)
     lk.set_group_bytes(0)
-    lpick = lk.autotune(trial_steps=16)
+    lpick = lk.autotune(trial_steps=64)
     lrows, lzc = lk.get_config()
     lk.set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
