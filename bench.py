@@ -19,10 +19,12 @@ Prints one JSON line.  Besides the metric:
   * accuracy: the timed run's port spectra against the oracle's stored run
     of the same 2000 steps, and the S-parameters of whole runs against the
     oracle's stored results;
-  * variants: plain FP64 and plain FP32 kernels on the same line (each
-    fraction from the same single-pass algorithmic bytes), the 400x120x80
-    microstrip, the 12-instance batched S-matrix (20 000 steps) against its
-    members run one at a time, the 16-instance sweep;
+  * variants: the same line by single steps and with the autotuner's
+    launch shape and temporal-block depth, plain FP64 and plain FP32
+    kernels on it (each fraction from the same single-pass algorithmic
+    bytes), the 400x120x80 microstrip, the 12-instance batched S-matrix
+    (20 000 steps; grouped, in lockstep, and its members run one at a time),
+    the 16-instance sweep;
   * ceilings: streaming copies of 1 GiB (the library's kernel, torch's);
   * cpu_baseline: the FP64 CPU oracle on a bounded sample of the same line,
     on all host threads and on one;
