@@ -199,11 +199,15 @@ hipError_t launch_plain_step(const DevGrid<T> &d, int64_t level, hipStream_t s, 
 {
     dim3 block(BX, BY, 1);
     dim3 grid((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, d.nz);
-    if (e0) hipEventRecord(e0, s);
+    if (e0) {
+        const hipError_t r = hipEventRecord(e0, s);
+        if (r != hipSuccess) return r;
+    }
     k_h_plain<T><<<grid, block, 0, s>>>(d);
     k_e_plain<T><<<grid, block, 0, s>>>(d, level);
-    if (e1) hipEventRecord(e1, s);
-    return hipGetLastError();
+    hipError_t r = hipGetLastError();
+    if (r == hipSuccess && e1) r = hipEventRecord(e1, s);
+    return r;
 }
 
 template <typename T>

@@ -338,6 +338,23 @@ def test_blow_up_is_reported_as_divergence(fd, fused):
     sim.close()
 
 
+@pytest.mark.parametrize("fused,steps", [(True, 600), (False, 2000)], ids=["fused", "plain64"])
+def test_unstable_time_step_is_reported_as_divergence(fd, fused, steps):
+    """A time step 1.2 times the 3-D stability limit on a grid with vacuum
+    cells: the leapfrog grows without bound until the fields overflow, and
+    fdtd_get_spectra reports DIVERGED rather than returning the sums.  (The
+    runs differ from normal ones only in the values, never in an index.)"""
+    p = W.small_microstrip(nsteps=steps)
+    p.courant = 1.2
+    sim = fd.Simulation(p, fused=fused, precision=fd.FP32 if fused else fd.FP64)
+    sim.run()
+    assert not np.all(np.isfinite(sim.field(W.EZ)))
+    with pytest.raises(fd.FdtdError) as e:
+        sim.spectra()
+    assert e.value.code == -6
+    sim.close()
+
+
 def test_fused_equals_plain_fp32(fd):
     p = W.small_microstrip(nsteps=300, seed=2, sigma_strip=5.8e7)
     a = fd.Simulation(p, fused=True).run()
