@@ -221,9 +221,10 @@ def bench_batch(fd, W, torch):
     probs = W.batched_smatrix(twin=True)
     nsteps = probs[0].nsteps
     bs = fd.BatchSimulation(probs)
-    # outside the timed region; resets.  64 trial steps: a grouped batch
-    # runs each group's trial in turn, and a group's first steps refill the
-    # memory-side cache
+    # outside the timed region; resets.  The search covers the schedule
+    # (grouped under the cache-sized budget, or lockstep) and the launch
+    # shape; 64 trial steps because a grouped trial runs each group's steps
+    # in turn and a group's first steps refill the memory-side cache
     pick = bs.autotune(trial_steps=64)
     rows, zc = bs.get_config()
     order = bs.tile_order()
@@ -247,6 +248,7 @@ def bench_batch(fd, W, torch):
     step_ms = bms / nsteps
     out = {"value": round(cells * nsteps / dt / 1e6, 1), "unit": "Mcell-updates/s",
            "timesteps": nsteps, "instances": len(probs), "cells": cells, "groups": groups,
+           "schedule": "lockstep" if groups == 1 else "grouped",
            "autotuned": {"candidate": pick, "tile_rows": rows, "zchunk": zc,
                          "tile_order": "automatic" if order[0] < 0 else order[0]},
            "avg_step_us": round(step_ms * 1e3, 2),
@@ -297,7 +299,7 @@ def bench_batch(fd, W, torch):
 def bench_sweep(fd, W, torch, nsteps=600):
     sp = W.geometry_sweep(nsteps=nsteps)
     ss = fd.BatchSimulation(sp)
-    pick = ss.autotune(trial_steps=16)
+    pick = ss.autotune(trial_steps=64)     # schedule and shape, as for the S-matrix batch
     rows, zc = ss.get_config()
     order = ss.tile_order()
     ss.set_timing(TIMING_EVERY)
@@ -315,6 +317,7 @@ def bench_sweep(fd, W, torch, nsteps=600):
     nbytes = sum(algorithmic_bytes(p)[0] for p in sp)
     return {"value": round(cells * nsteps / dt / 1e6, 1), "unit": "Mcell-updates/s",
             "timesteps": nsteps, "instances": len(sp), "cells": cells, "groups": groups,
+            "schedule": "lockstep" if groups == 1 else "grouped",
             "autotuned": {"candidate": pick, "tile_rows": rows, "zchunk": zc,
                           "tile_order": "automatic" if order[0] < 0 else order[0]},
             "avg_step_us": round(sms / nsteps * 1e3, 2),

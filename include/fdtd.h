@@ -285,12 +285,21 @@ fdtd_status fdtd_batch_run(fdtd_batch *batch, int64_t nsteps, void *stream);
 /* Choose the tile height (2, 4, 8, 12, 16 rows), z-chunk (4, 8, 16, 32, 64
  * planes) and tile order (automatic or 16, see fdtd_batch_set_tile_order) of the
  * batched kernel by timing each candidate
- * for `trial_steps` steps; the member states are reset afterwards.
+ * for `trial_steps` steps; the member states are reset afterwards.  When the
+ * member workspaces exceed the group budget (fdtd_batch_set_group_bytes), the
+ * schedule is chosen too: every shape is timed grouped and in lockstep (all
+ * members in one launch pair per step), and a lockstep win puts the batch in
+ * one group (fdtd_batch_get_groups then returns 1) until the next
+ * set_group_bytes.  A grouped trial runs each group's steps in turn, so
+ * trial_steps of 50 or more keep the refill of the memory-side cache at
+ * each group's start from weighing on it.
  * cache_path (may be NULL) names a JSON file keyed by GPU architecture and
  * member grid shapes: a hit applies the stored choice without timing
  * (*best_index = -1), a miss stores the winner.  Synchronous.  *best_index
- * receives the index of the chosen candidate in (rows, z-chunk, order)
- * lexicographic order (50 candidates).  On a
+ * receives the index of the chosen candidate in (schedule, rows, z-chunk,
+ * order) lexicographic order, the configured schedule first (50
+ * candidates per schedule).  Any choice gives the same results bit for
+ * bit.  On a
  * failure the launch shape is the last one tried and the member states are
  * undefined until fdtd_batch_reset. */
 fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const char *cache_path,

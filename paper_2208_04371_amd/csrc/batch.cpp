@@ -102,16 +102,17 @@ void compute_blocks(Batch &B)
     }
     B.nb_total = nb;
     B.ni_total = ni;
-    // groups: consecutive members packed greedily under group_bytes
+    // groups: consecutive members packed greedily under group_bytes (one
+    // group of all in lockstep)
     B.groups.clear();
     B.gsets = B.sets;
+    const size_t budget = B.cfg.lockstep ? 0 : B.group_bytes;
     size_t total = 0;
     for (const Plan *P : B.plans) total += P->ws_bytes;
     for (size_t q = 0; q < B.plans.size(); ++q) {
         const size_t w = B.plans[q]->ws_bytes;
         const bool fresh = B.groups.empty() ||
-                           (B.group_bytes > 0 && total > B.group_bytes &&
-                            B.groups.back().bytes + w > B.group_bytes);
+                           (budget > 0 && total > budget && B.groups.back().bytes + w > budget);
         if (fresh) B.groups.push_back({(int32_t)q, 0, 0, 0, 0});
         Batch::Group &g = B.groups.back();
         TileSet &t = B.gsets[q];
@@ -389,6 +390,7 @@ fdtd_status fdtd_batch_set_group_bytes(fdtd_batch *batch, uint64_t bytes)
     if (!batch) return FDTD_E_INVALID_ARG;
     return bguard(batch, [&]() {
         batch->group_bytes = (size_t)bytes;
+        batch->cfg.lockstep = 0;
         compute_blocks(*batch);
         if (batch->cfg_auto) default_config(*batch);
         if (batch->bound) upload_tables(*batch, nullptr);
@@ -437,9 +439,17 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
         BREQUIRE(B.bound, FDTD_E_STATE, "batch not bound");
         BREQUIRE(trial_steps >= 1, FDTD_E_INVALID_ARG, "trial_steps must be >= 1");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        // the grouped schedule launches per group: its best shape differs
+        // groups under the configured budget (a lockstep choice set aside)
+        const LaunchCfg keep = B.cfg;
+        B.cfg.lockstep = 0;
+        compute_blocks(B);
+        const size_t ngroups = B.groups.size();
+        B.cfg = keep;
+        compute_blocks(B);
+        // the grouped schedule launches per group: its best shape differs,
+        // and lockstep is searched beside it
         std::string key = tune_device_name() + "|" + tune_shape_key(B.plans.data(), B.plans.size());
-        if (B.groups.size() > 1) key += "groups=" + std::to_string(B.groups.size()) + ";";
+        if (ngroups > 1) key += "groups=" + std::to_string(ngroups) + ";";
         TimerPause pause(B.timer);   // trial launches are not the caller's
         TuneHooks h;
         h.apply = [&](const LaunchCfg &c) {
@@ -447,6 +457,7 @@ fdtd_status fdtd_batch_autotune(fdtd_batch *batch, int32_t trial_steps, const ch
             upload_tables(B, s);
         };
         h.run = [&](int32_t n) { batch_run(B, n, s); };
+        h.schedules = ngroups > 1 ? 2 : 1;
         LaunchCfg best = B.cfg;
         int32_t best_i = -1;
         hcheck(tune_search(h, trial_steps, cache_path, key, s, best, best_i), "autotune");

@@ -90,6 +90,8 @@ struct LaunchCfg {
     int32_t tb_zchunk = 16;  // two-level kernel: planes marched per block (4..256)
     int32_t tb_depth = 2;    // levels per pass of the two-level tiles of a plan
                              // with the third buffer: 2, or 1 (single steps)
+    int32_t lockstep = 0;    // batches: 1 = every member in one group whatever
+                             // the group budget (set by the autotuner)
     int32_t order = -1;      // block-to-tile order (see tile_order), -1 = automatic
     int32_t stream = -1;     // streaming field stores (see stream_stores), -1 = automatic
 };
@@ -363,6 +365,7 @@ struct TuneHooks {
     std::function<void(int32_t)> run;
     bool two_level = false;  // a plan with the third buffer: also search the
                              // depth and tile shape of its two-level passes
+    int32_t schedules = 1;   // 2: a grouped batch, searched grouped and in lockstep
 };
 // GPU architecture name of the current device (the cache key's first part).
 std::string tune_device_name();
@@ -371,7 +374,8 @@ std::string tune_shape_key(const Plan *const *plans, size_t n);
 // Times every candidate shape for trial_steps steps after one warm-up step
 // and applies the fastest; with cache_path, a stored shape for key is applied
 // instead (best_index = -1) and a timed winner is stored.  The first stage
-// searches (rows, z-chunk, order) in lexicographic order (index i1 < 50);
+// searches (schedule, rows, z-chunk, order) in lexicographic order (index
+// i1 < 50 * schedules; schedule 0 is the configured one, 1 lockstep);
 // with two_level, a second stage keeps that winner and searches two-level
 // passes over (tile rows, z-chunk) in lexicographic order, then single
 // steps (index i2 < 13).  best_index = i1 (+ 50 * i2 with two_level).

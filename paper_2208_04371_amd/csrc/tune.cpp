@@ -24,16 +24,17 @@ const int TUNE_Z[] = {4, 8, 16, 32, 64};
 const int TUNE_ORDER[] = {-1, 16};
 const int TUNE_TB_ROWS[] = {8, 10, 13};
 const int TUNE_TB_Z[] = {8, 16, 32, 64};
-constexpr int TUNE_STAGE1 = 5 * 5 * 2;
+constexpr int TUNE_STAGE1 = 5 * 5 * 2;   // per schedule
 
 // The cache is a JSON object written one entry per line:
 //   {
-//   "gfx950:...|400x120x80;": [4, 32, 0.0312, 0, 2, 13, 16],
+//   "gfx950:...|400x120x80;": [4, 32, 0.0312, 0, 2, 13, 16, 0],
 //   ...
 //   }
 // (rows, z-chunk, milliseconds per step, tile order, two-level depth, tile
-// rows and z-chunk; an entry without the order leaves it automatic, one
-// without the last three leaves the two-level defaults).  Unknown lines are
+// rows and z-chunk, lockstep; an entry without the order leaves it
+// automatic, one without the two-level fields the two-level defaults, one
+// without the last field the configured schedule).  Unknown lines are
 // ignored.
 std::vector<std::pair<std::string, std::string>> cache_read(const char *path)
 {
@@ -58,18 +59,20 @@ bool cache_lookup(const char *path, const std::string &key, LaunchCfg &cfg)
 {
     for (const auto &e : cache_read(path)) {
         if (e.first != key) continue;
-        int rows = 0, z = 0, order = -1, depth = 2, tbr = 13, tbz = 16;
+        int rows = 0, z = 0, order = -1, depth = 2, tbr = 13, tbz = 16, lock = 0;
         double ms = 0;
-        const int n = std::sscanf(e.second.c_str(), "%d , %d , %lf , %d , %d , %d , %d", &rows, &z,
-                                  &ms, &order, &depth, &tbr, &tbz);
+        const int n = std::sscanf(e.second.c_str(), "%d , %d , %lf , %d , %d , %d , %d , %d", &rows,
+                                  &z, &ms, &order, &depth, &tbr, &tbz, &lock);
         if (n >= 2 && valid_rows(rows) && z >= 1 && z <= 64 && valid_order(order) &&
-            (depth == 1 || depth == 2) && valid_tb_rows(tbr) && tbz >= 4 && tbz <= 256) {
+            (depth == 1 || depth == 2) && valid_tb_rows(tbr) && tbz >= 4 && tbz <= 256 &&
+            (lock == 0 || lock == 1)) {
             cfg.rows = rows;
             cfg.zchunk = z;
             cfg.order = order;
             cfg.tb_depth = depth;
             cfg.tb_rows = tbr;
             cfg.tb_zchunk = tbz;
+            cfg.lockstep = lock;
             return true;
         }
         return false;
@@ -81,8 +84,8 @@ void cache_store(const char *path, const std::string &key, const LaunchCfg &cfg,
 {
     auto entries = cache_read(path);
     char val[128];
-    std::snprintf(val, sizeof val, "%d, %d, %.6g, %d, %d, %d, %d", cfg.rows, cfg.zchunk, ms,
-                  cfg.order, cfg.tb_depth, cfg.tb_rows, cfg.tb_zchunk);
+    std::snprintf(val, sizeof val, "%d, %d, %.6g, %d, %d, %d, %d, %d", cfg.rows, cfg.zchunk, ms,
+                  cfg.order, cfg.tb_depth, cfg.tb_rows, cfg.tb_zchunk, cfg.lockstep);
     bool found = false;
     for (auto &e : entries)
         if (e.first == key) { e.second = val; found = true; }
@@ -164,18 +167,20 @@ hipError_t tune_search(const TuneHooks &h, int32_t trial_steps, const char *cach
     float best = 1e30f;
     int idx = 0;
     best_index = -1;
-    for (int r : TUNE_ROWS)
-        for (int z : TUNE_Z)
-            for (int o : TUNE_ORDER) {
-                LaunchCfg c;
-                c.rows = r;
-                c.zchunk = z;
-                c.order = o;
-                float ms = 0;
-                if ((e = time_one(c, ms)) != hipSuccess) return e;
-                if (ms < best) { best = ms; best_index = idx; best_cfg = c; }
-                ++idx;
-            }
+    for (int sch = 0; sch < h.schedules; ++sch)
+        for (int r : TUNE_ROWS)
+            for (int z : TUNE_Z)
+                for (int o : TUNE_ORDER) {
+                    LaunchCfg c;
+                    c.rows = r;
+                    c.zchunk = z;
+                    c.order = o;
+                    c.lockstep = sch;
+                    float ms = 0;
+                    if ((e = time_one(c, ms)) != hipSuccess) return e;
+                    if (ms < best) { best = ms; best_index = idx; best_cfg = c; }
+                    ++idx;
+                }
     if (h.two_level) {
         // the winner's launch shape with each two-level tile shape, then
         // with single steps; all timed afresh, so the stage compares like

@@ -136,7 +136,7 @@ def test_plan_autotune_chooses_temporal_depth(fd, tmp_path):
     (key, val), = entries.items()
     assert key.endswith("|256x64x48;two-level")
     assert val[:2] == [rows, z] and val[3] == order
-    assert val[4] == (1 if i2 == 12 else 2) and val[5:] == [tbr, tbz]
+    assert val[4] == (1 if i2 == 12 else 2) and val[5:7] == [tbr, tbz] and val[7] == 0
     sim.run()
     ref = fd.Simulation(p, fused=True, temporal=0, config=(rows, z))
     ref.set_tile_order(order)
@@ -155,4 +155,46 @@ def test_plan_autotune_chooses_temporal_depth(fd, tmp_path):
     fd.fdtd_plan_set_temporal_config(again.handle, 13, 16)
     assert again.temporal()[1:4] == (1, 13, 16)
     for x in (sim, ref, again):
+        x.close()
+
+
+def test_batch_autotune_chooses_the_schedule(fd, tmp_path):
+    """A batch split into groups (a 1-byte budget: one member per group):
+    the search times every shape grouped and in lockstep (100 candidates)
+    and applies the winner's schedule; results equal the single runs bit for
+    bit either way, and the cached choice brings the schedule back."""
+    cache = str(tmp_path / "tune.json")
+    probs = _probs()
+    bs = fd.BatchSimulation(probs)
+    bs.set_group_bytes(1)
+    assert bs.groups() == 3
+    best = bs.autotune(trial_steps=8, cache_path=cache)
+    rows, z = bs.get_config()
+    lock = best // 50
+    print(f"batch autotune picked {best}: {'lockstep' if lock else 'grouped'}, rows {rows} "
+          f"z {z}", flush=True)
+    assert 0 <= best < 100
+    assert bs.groups() == (1 if lock else 3)
+    with open(cache) as f:
+        entries = json.load(f)
+    (key, val), = entries.items()
+    assert key.endswith("96x36x28;96x40x28;96x44x28;groups=3;")
+    assert val[:2] == [rows, z] and val[7] == lock
+    bs.run(60)
+    for q, p in enumerate(probs):
+        ref = fd.Simulation(p, fused=True, config=(rows, z))
+        ref.run(60)
+        assert np.array_equal(bs.field(q, W.EZ), ref.field(W.EZ))
+        Va, Ia = bs.spectra(q)
+        Vb, Ib = ref.spectra()
+        assert np.array_equal(Va, Vb) and np.array_equal(Ia, Ib)
+        ref.close()
+    again = fd.BatchSimulation(probs)
+    again.set_group_bytes(1)
+    assert again.autotune(trial_steps=8, cache_path=cache) == -1
+    assert again.get_config() == (rows, z) and again.groups() == bs.groups()
+    # a budget set by the caller takes the schedule back from the autotuner
+    again.set_group_bytes(1)
+    assert again.groups() == 3
+    for x in (bs, again):
         x.close()
