@@ -390,7 +390,7 @@ fdtd_status fdtd_plan_get_stream_stores(const fdtd_plan *plan, int32_t *mode, in
  * INVALID_ARG for other modes; UNSUPPORTED for mode 1 on a PLAIN plan.
  * Such plans cannot join a batch.
  * set_temporal_config: the two-level tiles are 60 cells in x, tile_rows
- * (8, 10 or 13) in y and zchunk (4..256) planes in z; default 13 x 16.
+ * (8, 10 or 13) in y and zchunk (4..256) planes in z; default 13 x 32.
  * It also makes the plan take two-level passes again where the autotuner
  * chose single steps (depth 1, fdtd_plan_autotune).
  * INVALID_ARG for other values.  Takes effect at the next run.

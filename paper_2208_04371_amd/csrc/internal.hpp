@@ -87,7 +87,7 @@ struct LaunchCfg {
     int32_t rows = 4;        // tile rows (y) per block of the fused kernel
     int32_t zchunk = 32;     // planes marched per block
     int32_t tb_rows = 13;    // two-level kernel: tile rows (8, 10 or 13)
-    int32_t tb_zchunk = 16;  // two-level kernel: planes marched per block (4..256)
+    int32_t tb_zchunk = 32;  // two-level kernel: planes marched per block (4..256)
     int32_t tb_depth = 2;    // levels per pass of the two-level tiles of a plan
                              // with the third buffer: 2, or 1 (single steps)
     int32_t lockstep = 0;    // batches: 1 = every member in one group whatever

@@ -59,7 +59,7 @@ bool cache_lookup(const char *path, const std::string &key, LaunchCfg &cfg)
 {
     for (const auto &e : cache_read(path)) {
         if (e.first != key) continue;
-        int rows = 0, z = 0, order = -1, depth = 2, tbr = 13, tbz = 16, lock = 0;
+        int rows = 0, z = 0, order = -1, depth = 2, tbr = 13, tbz = 32, lock = 0;
         double ms = 0;
         const int n = std::sscanf(e.second.c_str(), "%d , %d , %lf , %d , %d , %d , %d , %d", &rows,
                                   &z, &ms, &order, &depth, &tbr, &tbz, &lock);

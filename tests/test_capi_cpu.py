@@ -322,7 +322,7 @@ def test_two_level_mode_and_shape_arguments(fd):
     p = W.small_microstrip()
     h = describe(p, fused=True)
     try:
-        assert fdtd_plan_get_temporal(h)[:4] == (-1, 0, 13, 16)
+        assert fdtd_plan_get_temporal(h)[:4] == (-1, 0, 13, 32)
         for bad in (-2, 2):
             with pytest.raises(fd.FdtdError) as e:
                 fdtd_plan_set_temporal(h, bad)
