@@ -198,3 +198,36 @@ def test_batch_autotune_chooses_the_schedule(fd, tmp_path):
     assert again.groups() == 3
     for x in (bs, again):
         x.close()
+
+
+def test_autotune_cache_entries_bad_and_old(fd, tmp_path):
+    """The cache is a file anyone can edit: an entry whose values are out of
+    range is ignored (the search runs and rewrites it), and an entry in the
+    older four-value form (rows, z-chunk, ms, order) still applies, with the
+    other fields at their defaults."""
+    cache = str(tmp_path / "tune.json")
+    p = W.small_microstrip(nsteps=30, ny=40, seed=5)
+    sim = fd.Simulation(p, fused=True)
+    assert sim.autotune(trial_steps=2, cache_path=cache) >= 0
+    with open(cache) as f:
+        (key, val), = json.load(f).items()
+    assert len(val) == 8
+    with open(cache, "w") as f:
+        f.write('{\n"%s": [7, 16, 0.05, 16, 2, 13, 32, 0],\nnot an entry\n}\n' % key)
+    assert sim.autotune(trial_steps=2, cache_path=cache) >= 0     # rows 7: ignored
+    with open(cache) as f:
+        val = json.load(f)[key]
+    assert val[0] in (2, 4, 8, 12, 16)
+    with open(cache, "w") as f:
+        f.write('{\n"%s": [4, 16, 0.05, 16]\n}\n' % key)
+    assert sim.autotune(trial_steps=2, cache_path=cache) == -1
+    assert sim.get_config() == (4, 16) and sim.tile_order()[0] == 16
+    sim.run()
+    ref = fd.Simulation(p, fused=True, config=(4, 16))
+    ref.set_tile_order(16)
+    ref.run()
+    Va, Ia = sim.spectra()
+    Vb, Ib = ref.spectra()
+    assert np.array_equal(Va, Vb) and np.array_equal(Ia, Ib)
+    for x in (sim, ref):
+        x.close()
