@@ -354,8 +354,11 @@ fdtd_status fdtd_batch_set_tile_order(fdtd_batch *batch, int32_t order);
  * the state still hits it and the outcome depends on the grid (a 296 MiB
  * microstrip gains 5 %, sweep grids of 289 and 308 MiB lose heavily).
  * mode: 1 on, 0 off, -1 (default) automatic, on for a launch whose
- * workspace (a batch: its group's) exceeds 512 MiB.  Results
- * do not depend on it.  INVALID_ARG for other modes.  The plan getter
+ * workspace (a batch: its group's) exceeds 512 MiB.  It applies to the
+ * single-level launches; the two-level pass (fdtd_plan_set_temporal) always
+ * stores through the cache, since its 60-cell rows do not start on 128-byte
+ * lines and the cache merges the partial lines of neighbouring tiles.
+ * Results do not depend on it.  INVALID_ARG for other modes.  The plan getter
  * returns the setting and (*used) the mode its launches use, from the
  * workspace size once known. */
 fdtd_status fdtd_batch_set_stream_stores(fdtd_batch *batch, int32_t mode);
